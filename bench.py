@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Coupled-step throughput of the MI355X central-moment LB step.
+
+One step = one pass of the whole hot path (pull-streaming, moments, LDS halo,
+gradients, forces, the four central-moment collisions, store) over every
+lattice of the workload.  Prints ONE JSON line on stdout:
+
+  value        whole-job MLUPS (lattice-node updates of all four sets / s / 1e6),
+               inputs resident in HBM, timed over exactly --steps steps
+  roofline     the step kernel's algorithmic HBM bytes (36 population loads +
+               36 stores per node) per launch / its average launch duration
+               (HIP events on the launch stream), against 8 TB/s
+  cpu_baseline the FP64 oracle timed on the host cores over a bounded sample
+
+Default workload: the four 1024x512 FP32 channels (NF and SRF at beta_s 0 and
+0.2), advanced together in one launch per step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {0: 576, 1: 288, 2: 144}  # 72 populations x storage bytes
+DTYPE = {0: "f64", 1: "f32", 2: "f16-storage/f32"}
+
+
+def workload(name: str):
+    from paper_2408_00146_amd import cases
+
+    if name == "fp32_1024x512x4":
+        return cases.config_fp32_runs()
+    if name == "fp64_128x64":
+        return [cases.config_small_fp64()]
+    if name.startswith(("fp16s_", "fp32_", "fp64_")) and name.endswith("2048x1024"):
+        prec = {"fp16s": cases.FP16S, "fp32": cases.FP32, "fp64": cases.FP64}[name.split("_")[0]]
+        return [cases.config_precision(prec)]
+    if name == "batched64":
+        return cases.config_batched()
+    if name == "large_plus_small":
+        return cases.config_large_plus_small()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(params: dict, budget_s: float = 15.0) -> dict:
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+
+    o = O.Oracle(params)
+    t = time.perf_counter()
+    o.step(2)
+    per = max((time.perf_counter() - t) / 2, 1e-6)
+    n = max(2, min(2000, int(budget_s / per)))
+    t = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t
+    cells = params["nx"] * params["ny"]
+    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "sample": f"one {params['nx']}x{params['ny']} channel of the workload, {n} steps from the "
+                      f"initial state, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="fp32_1024x512x4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not code)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_00146_amd import lbm
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    ps = workload(args.workload)
+    cells = sum(p["nx"] * p["ny"] for p in ps)
+    alg_bytes = sum(p["nx"] * p["ny"] * BYTES_PER_NODE[p["precision"]] for p in ps)
+    precs = sorted({p["precision"] for p in ps})
+
+    s = lbm.Solver(ps)
+    if args.tile is not None:
+        s.set_tile(args.tile)
+    elif not args.no_autotune:
+        s.autotune(10)
+    shape = lbm.tile_shapes()[s.tile]
+    log(f"workload {args.workload}: {len(ps)} case(s), {cells} nodes, tile {shape}")
+
+    s.step(args.warmup)
+    s.synchronize()
+    s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, nlaunch = s.kernel_time_ms()
+    s.set_kernel_timing(False)
+    for i in range(min(len(ps), 4)):
+        d = s.reduce(i)
+        log(f"case {i}: step {d['step']} xc {d['xc']:.3f} ux {d['ux']:.3e} nonfinite {d['nonfinite']}")
+
+    mlups = cells * args.steps / dt / 1e6
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    line = {
+        "metric": "coupled-step MLUPS + % HBM roofline; batched/FP16-store vs plain FP32",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "+".join(DTYPE[p] for p in precs),
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cases": len(ps), "nodes": cells,
+                   "grids": sorted({f"{p['nx']}x{p['ny']}" for p in ps}),
+                   "tile": list(shape), "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step", "avg_launch_ms": round(kms, 5), "launches": nlaunch,
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ps[0])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,935 @@
+// lbm.hip -- gfx950 kernels and the C-ABI host runtime (include/lbm.h) of the
+// coupled central-moment LB step of arXiv 2408.00146.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// Tile shapes compiled into the library (BX x BY nodes per 256-thread workgroup).
+struct Shape {
+    int bx, by;
+};
+constexpr Shape kShapes[] = {{64, 8}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kMacroBX = 64, kMacroBY = 8;
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
+// Remap so that each XCD walks one contiguous band of the tile table: the
+// halo rows shared by vertically adjacent tiles then hit that XCD's own L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, xcd = b & 7, slot = b >> 3;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+template <typename R, int BX, int BY>
+__global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
+                                              int ntiles, const int64_t* __restrict__ steps, int t)
+{
+    __shared__ Smem<R, BX, BY> sh;
+    const TileRec tr = tiles[xcd_remap(blockIdx.x, ntiles)];
+    const CaseDev& cd = cases[tr.c];
+    const int64_t s = steps[tr.c] + t;
+    if (cd.max_steps > 0 && s >= cd.max_steps) return;  // uniform over the block
+    Ctx<R> c;
+    c.load(cd);
+    const MacroOut mo{nullptr, 0u, nullptr};
+    if constexpr (sizeof(R) == 8) {
+        tile_body<double, double, BX, BY, MODE_STEP>(c, tr.x0, tr.y0, (const double*)cd.buf[s & 1],
+                                                     (double*)cd.buf[(s + 1) & 1], sh, mo, nullptr);
+    } else {
+        if (cd.prec == PREC_FP16S)
+            tile_body<float, __half, BX, BY, MODE_STEP>(c, tr.x0, tr.y0, (const __half*)cd.buf[s & 1],
+                                                        (__half*)cd.buf[(s + 1) & 1], sh, mo, nullptr);
+        else
+            tile_body<float, float, BX, BY, MODE_STEP>(c, tr.x0, tr.y0, (const float*)cd.buf[s & 1],
+                                                       (float*)cd.buf[(s + 1) & 1], sh, mo, nullptr);
+    }
+}
+
+// Deterministic block reduction of the diagnostic partials: wave64 butterfly
+// then a fixed-order pass over the 4 waves.  Slots 11, 13 are minima, 12, 14
+// maxima, the rest sums.
+__device__ __forceinline__ double combine(int k, double a, double b)
+{
+    if (k == 11 || k == 13) return fmin(a, b);
+    if (k == 12 || k == 14) return fmax(a, b);
+    return a + b;
+}
+
+__device__ void block_reduce(double v[NDIAG_PART], double (*red)[NDIAG_PART], double* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NDIAG_PART; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) x = combine(k, x, __shfl_xor(x, m, 64));
+        v[k] = x;
+    }
+    if (lane == 0)
+        for (int k = 0; k < NDIAG_PART; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < NDIAG_PART) {
+        const int k = threadIdx.x;
+        double x = red[0][k];
+        for (int w = 1; w < 4; ++w) x = combine(k, x, red[w][k]);
+        out[k] = x;
+    }
+}
+
+__device__ __forceinline__ void diag_init(double d[NDIAG_PART])
+{
+#pragma unroll
+    for (int k = 0; k < NDIAG_PART; ++k) d[k] = 0.0;
+    d[11] = INFINITY;
+    d[12] = -INFINITY;
+    d[13] = INFINITY;
+    d[14] = -INFINITY;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_macro(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
+                                               int tile0, const int64_t* __restrict__ steps, int case_id,
+                                               uint32_t mask, double* fields, double* partials)
+{
+    __shared__ Smem<R, kMacroBX, kMacroBY> sh;
+    __shared__ double red[4][NDIAG_PART];
+    const TileRec tr = tiles[tile0 + blockIdx.x];
+    const CaseDev& cd = cases[case_id];
+    const int64_t s = steps[case_id];
+    Ctx<R> c;
+    c.load(cd);
+    const MacroOut mo{fields, mask, partials};
+    double acc[NDIAG_PART];
+    diag_init(acc);
+    double* dacc = partials ? acc : nullptr;
+    if constexpr (sizeof(R) == 8) {
+        tile_body<double, double, kMacroBX, kMacroBY, MODE_MACRO>(c, tr.x0, tr.y0, (const double*)cd.buf[s & 1],
+                                                                  nullptr, sh, mo, dacc);
+    } else {
+        if (cd.prec == PREC_FP16S)
+            tile_body<float, __half, kMacroBX, kMacroBY, MODE_MACRO>(c, tr.x0, tr.y0, (const __half*)cd.buf[s & 1],
+                                                                     nullptr, sh, mo, dacc);
+        else
+            tile_body<float, float, kMacroBX, kMacroBY, MODE_MACRO>(c, tr.x0, tr.y0, (const float*)cd.buf[s & 1],
+                                                                    nullptr, sh, mo, dacc);
+    }
+    if (partials) block_reduce(acc, red, partials + (int64_t)blockIdx.x * NDIAG_PART);
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partials, int nblocks, double* out)
+{
+    __shared__ double red[4][NDIAG_PART];
+    double acc[NDIAG_PART];
+    diag_init(acc);
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < NDIAG_PART; ++k) acc[k] = combine(k, acc[k], partials[(int64_t)b * NDIAG_PART + k]);
+    block_reduce(acc, red, out);
+}
+
+__global__ void k_advance(const CaseDev* __restrict__ cases, int ncases, int64_t* steps, int64_t k)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncases) return;
+    int64_t s = steps[i] + k;
+    if (cases[i].max_steps > 0 && s > cases[i].max_steps) s = cases[i].max_steps;
+    if (steps[i] < s) steps[i] = s;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014), k-th output of the sequence seeded
+// with `seed`; 53 high bits mapped to [-1, 1).
+__device__ __forceinline__ double noise_unit(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+struct InitDev {
+    int32_t kind, pad;
+    double xc, yc, R, W, psi_bulk, psi_band, phi_noise;
+    uint64_t seed;
+};
+
+// Rest-equilibrium populations X_a = w_a X of given phi, T, psi (g = 0 for
+// p = 0, u = 0), encoded into buffer `b` of the case.  Null field pointers
+// select the built-in initial condition (tanh interface (Sec. 3) + noise,
+// linear wall law for T, psi band).
+template <typename S, typename R>
+__device__ void init_node(const CaseDev& cd, const InitDev& in, int b, int x, int y, const double* phi_in,
+                          const double* T_in, const double* psi_in)
+{
+    const int64_t k = (int64_t)y * cd.nx + x;
+    double phi, T, psi;
+    if (phi_in) {
+        phi = phi_in[k];
+        T = T_in[k];
+        psi = psi_in[k];
+    } else {
+        double d = 0.0, pc = 0.0;
+        if (in.kind != 2) {
+            if (in.kind == 1) d = in.R - fabs((double)y - in.yc);
+            else d = in.R - sqrt(((double)x - in.xc) * ((double)x - in.xc) + ((double)y - in.yc) * ((double)y - in.yc));
+            pc = 0.5 + 0.5 * tanh(2.0 * d / in.W);
+        }
+        phi = pc + in.phi_noise * noise_unit(in.seed, (uint64_t)k);
+        T = cd.T0 + cd.gradT * ((double)x - cd.xT0);
+        psi = in.psi_bulk + in.psi_band * 4.0 * pc * (1.0 - pc);
+    }
+    const double Tr = cd.refs ? cd.T0 + cd.gradT * ((double)x - cd.xT0) : 0.0;
+    const double qr = cd.refs ? cd.ref_q : 0.0;
+    S* buf = (S*)cd.buf[b];
+    const int64_t o = (int64_t)y * cd.pitch + x;
+    const R sc = R(cd.scale);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const double w = wt(a);
+        buf[(int64_t)(SET_F * 9 + a) * cd.plane + o] = enc<S, R>(R(w * phi), sc);
+        buf[(int64_t)(SET_G * 9 + a) * cd.plane + o] = enc<S, R>(R(0), sc);
+        buf[(int64_t)(SET_H * 9 + a) * cd.plane + o] = enc<S, R>(R(w * (T - Tr)), sc);
+        buf[(int64_t)(SET_Q * 9 + a) * cd.plane + o] = enc<S, R>(R(w * (psi - qr)), sc);
+    }
+}
+
+__global__ void k_init(const CaseDev* __restrict__ cases, int case_id, InitDev in, int b, const double* phi_in,
+                       const double* T_in, const double* psi_in)
+{
+    const CaseDev& cd = cases[case_id];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= cd.nx || y >= cd.ny) return;
+    if (cd.prec == PREC_FP64) init_node<double, double>(cd, in, b, x, y, phi_in, T_in, psi_in);
+    else if (cd.prec == PREC_FP16S) init_node<__half, float>(cd, in, b, x, y, phi_in, T_in, psi_in);
+    else init_node<float, float>(cd, in, b, x, y, phi_in, T_in, psi_in);
+}
+
+// Populations <-> FP64 planes [4][9][ny][nx] (full values, references added).
+template <typename S, typename R>
+__device__ void pops_node(const CaseDev& cd, int b, int x, int y, double* out, const double* in)
+{
+    const int64_t n = (int64_t)cd.nx * cd.ny, k = (int64_t)y * cd.nx + x;
+    const double ref[4] = {0.0, 0.0, cd.refs ? cd.T0 + cd.gradT * ((double)x - cd.xT0) : 0.0,
+                           cd.refs ? cd.ref_q : 0.0};
+    S* buf = (S*)cd.buf[b];
+    const int64_t o = (int64_t)y * cd.pitch + x;
+    for (int set = 0; set < 4; ++set)
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int64_t i = (int64_t)(set * 9 + a) * cd.plane + o;
+            const int64_t j = (int64_t)(set * 9 + a) * n + k;
+            if (out) out[j] = (double)dec<S, R>(buf[i], R(cd.inv_scale)) + wt(a) * ref[set];
+            else buf[i] = enc<S, R>(R(in[j] - wt(a) * ref[set]), R(cd.scale));
+        }
+}
+
+__global__ void k_pops(const CaseDev* __restrict__ cases, int case_id, int b, double* out, const double* in)
+{
+    const CaseDev& cd = cases[case_id];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= cd.nx || y >= cd.ny) return;
+    if (cd.prec == PREC_FP64) pops_node<double, double>(cd, b, x, y, out, in);
+    else if (cd.prec == PREC_FP16S) pops_node<__half, float>(cd, b, x, y, out, in);
+    else pops_node<float, float>(cd, b, x, y, out, in);
+}
+
+}  // namespace lbm
+
+// ======================================================================= host
+using namespace lbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(LBM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t elem_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
+
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * pitch_of(c.nx) * c.ny * elem_bytes(c.precision)); }
+
+int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
+
+struct Layout {
+    size_t off_cases, off_steps, off_partials, off_diag, off_tiles[kNumShapes], off_mtiles, off_pops, total;
+    int64_t ntiles[kNumShapes], nmtiles, max_case_mtiles;
+};
+
+Layout layout_of(const lbm_case* cs, int n)
+{
+    Layout L{};
+    size_t o = 0;
+    L.off_cases = o;
+    o = align256(o + sizeof(CaseDev) * n);
+    L.off_steps = o;
+    o = align256(o + sizeof(int64_t) * n);
+    int64_t mt = 0, mmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t t = tiles_of(cs[i], kMacroBX, kMacroBY);
+        mt += t;
+        mmax = std::max(mmax, t);
+    }
+    L.nmtiles = mt;
+    L.max_case_mtiles = mmax;
+    L.off_partials = o;
+    o = align256(o + sizeof(double) * NDIAG_PART * (size_t)std::max<int64_t>(mmax, 1));
+    L.off_diag = o;
+    o = align256(o + sizeof(double) * NDIAG_PART);
+    for (int s = 0; s < kNumShapes; ++s) {
+        int64_t t = 0;
+        for (int i = 0; i < n; ++i) t += tiles_of(cs[i], kShapes[s].bx, kShapes[s].by);
+        L.ntiles[s] = t;
+        L.off_tiles[s] = o;
+        o = align256(o + sizeof(TileRec) * (size_t)t);
+    }
+    L.off_mtiles = o;
+    o = align256(o + sizeof(TileRec) * (size_t)mt);
+    L.off_pops = o;
+    for (int i = 0; i < n; ++i) o += 2 * case_pop_bytes(cs[i]);
+    L.total = o;
+    return L;
+}
+
+int validate(const lbm_case& c, int i)
+{
+    if (c.nx < 4 || c.ny < 4) return fail(LBM_E_INVAL, "case %d: nx, ny must be >= 4", i);
+    if ((int64_t)c.nx * c.ny > (int64_t)1 << 28) return fail(LBM_E_INVAL, "case %d: lattice too large", i);
+    if (c.precision < 0 || c.precision > 2) return fail(LBM_E_INVAL, "case %d: precision", i);
+    if (c.sigma_law < 0 || c.sigma_law > 1) return fail(LBM_E_INVAL, "case %d: sigma_law", i);
+    if (c.init_kind < 0 || c.init_kind > 2) return fail(LBM_E_INVAL, "case %d: init_kind", i);
+    if (c.wall[0] != c.wall[1] || c.wall[2] != c.wall[3])
+        return fail(LBM_E_INVAL, "case %d: wall: periodic sides must come in pairs", i);
+    for (int s = 0; s < 4; ++s)
+        if (c.wall[s] > 1 || c.t_bc[s] > 1 || c.psi_bc[s] > 1) return fail(LBM_E_INVAL, "case %d: wall/t_bc/psi_bc flags", i);
+    struct {
+        const char* name;
+        double v;
+    } pos[] = {{"W", c.W}, {"rho_A", c.rho_A}, {"rho_B", c.rho_B}, {"nu_A", c.nu_A}, {"nu_B", c.nu_B},
+               {"alpha_A", c.alpha_A}, {"alpha_B", c.alpha_B}, {"D_psi", c.D_psi}, {"M_phi", c.M_phi},
+               {"psi_inf", c.psi_inf}};
+    for (auto& p : pos)
+        if (!(p.v > 0) || !std::isfinite(p.v)) return fail(LBM_E_INVAL, "case %d: %s must be finite and > 0", i, p.name);
+    if (c.sigma_law == LBM_SIGMA_PAPER && !(c.T_ref != 0)) return fail(LBM_E_INVAL, "case %d: T_ref must be nonzero", i);
+    return LBM_OK;
+}
+
+CaseDev make_dev(const lbm_case& c, void* b0, void* b1)
+{
+    CaseDev d{};
+    d.nx = c.nx;
+    d.ny = c.ny;
+    d.pitch = pitch_of(c.nx);
+    d.prec = c.precision;
+    d.wallx = c.wall[0];
+    d.wally = c.wall[2];
+    d.law = c.sigma_law;
+    d.refs = c.precision == LBM_FP64 ? 0 : 1;
+    for (int s = 0; s < 4; ++s) {
+        d.tbc[s] = c.wall[s] ? c.t_bc[s] : 0;
+        d.pbc[s] = c.wall[s] ? c.psi_bc[s] : 0;
+        d.psi_w[s] = c.psi_w[s];
+    }
+    d.T0 = c.T0;
+    d.gradT = c.gradT;
+    d.xT0 = c.xT0;
+    d.s0 = c.sigma0;
+    d.sT = c.sigma_T;
+    d.sTT = c.sigma_TT;
+    d.Tref = c.T_ref;
+    d.beta = c.beta_s;
+    d.inv_psi_inf = 1.0 / c.psi_inf;
+    d.rhoA = c.rho_A;
+    d.drho = c.rho_B - c.rho_A;
+    d.muA = c.rho_A * c.nu_A;
+    d.dmu = c.rho_B * c.nu_B - c.rho_A * c.nu_A;
+    d.alphaA = c.alpha_A;
+    d.dalpha = c.alpha_B - c.alpha_A;
+    d.om_phi = 1.0 / (3.0 * c.M_phi + 0.5);
+    d.om_psi = 1.0 / (3.0 * c.D_psi + 0.5);
+    d.Mphi = c.M_phi;
+    d.W = c.W;
+    d.Dpsi = c.D_psi;
+    d.s_lam = c.s_lam;
+    d.w_lam = c.w_lam;
+    d.Fx = c.Fext_x;
+    d.Fy = c.Fext_y;
+    d.grav = c.gravity;
+    d.ref_q = c.psi_bulk;
+    d.scale = c.precision == LBM_FP16S ? 1024.0 : 1.0;
+    d.inv_scale = 1.0 / d.scale;
+    d.plane = (int64_t)c.ny * d.pitch;
+    d.max_steps = c.max_steps;
+    d.buf[0] = b0;
+    d.buf[1] = b1;
+    return d;
+}
+
+InitDev make_init(const lbm_case& c)
+{
+    InitDev in{};
+    in.kind = c.init_kind;
+    in.xc = c.xc;
+    in.yc = c.yc;
+    in.R = c.R;
+    in.W = c.W;
+    in.psi_bulk = c.psi_bulk;
+    in.psi_band = c.psi_band;
+    in.phi_noise = c.phi_noise;
+    in.seed = c.seed;
+    return in;
+}
+
+using StepKernel = void (*)(const CaseDev*, const TileRec*, int, const int64_t*, int);
+
+template <typename R>
+StepKernel step_kernel(int shape)
+{
+    switch (shape) {
+        case 0: return k_step<R, 64, 8>;
+        case 1: return k_step<R, 64, 16>;
+        case 2: return k_step<R, 64, 32>;
+        case 3: return k_step<R, 32, 32>;
+        case 4: return k_step<R, 128, 8>;
+        case 5: return k_step<R, 128, 16>;
+    }
+    return nullptr;
+}
+
+// FP64 tiles must fit the 64 KiB per-workgroup LDS budget.
+bool shape_ok(int shape, bool fp64)
+{
+    const int bx = kShapes[shape].bx, by = kShapes[shape].by;
+    const size_t lds = (size_t)((bx + 4) * (by + 4) + 4 * (bx + 2) * (by + 2)) * (fp64 ? 8 : 4);
+    return lds <= 65536;
+}
+
+}  // namespace
+
+struct lbm_handle {
+    int ncases = 0;
+    std::vector<lbm_case> cases;
+    std::vector<CaseDev> dev;
+    std::vector<int64_t> steps;       // host mirror of the device step counters
+    std::vector<int64_t> mtile_begin, mtile_count;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L{};
+    bool fp64 = false;
+    int shape = 1;
+    bool use_graph = true;
+    bool timing = false;
+    std::map<int, hipGraphExec_t> graphs;
+    std::vector<hipEvent_t> ev;       // pairs around timed step launches
+    int64_t timed = 0;
+
+    CaseDev* d_cases() { return (CaseDev*)(ws + L.off_cases); }
+    int64_t* d_steps() { return (int64_t*)(ws + L.off_steps); }
+    double* d_partials() { return (double*)(ws + L.off_partials); }
+    double* d_diag() { return (double*)(ws + L.off_diag); }
+    TileRec* d_tiles(int s) { return (TileRec*)(ws + L.off_tiles[s]); }
+    TileRec* d_mtiles() { return (TileRec*)(ws + L.off_mtiles); }
+
+    int launch_step(int t)
+    {
+        StepKernel k = fp64 ? step_kernel<double>(shape) : step_kernel<float>(shape);
+        const int64_t nt = L.ntiles[shape];
+        if (nt <= 0) return LBM_OK;
+        hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream, d_cases(), d_tiles(shape), (int)nt,
+                           d_steps(), t);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    int launch_advance(int64_t k)
+    {
+        hipLaunchKernelGGL(k_advance, dim3((ncases + 255) / 256), dim3(256), 0, stream, d_cases(), ncases, d_steps(), k);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    void host_advance(int64_t k)
+    {
+        for (int i = 0; i < ncases; ++i) {
+            int64_t s = steps[i] + k;
+            if (cases[i].max_steps > 0 && s > cases[i].max_steps) s = cases[i].max_steps;
+            if (steps[i] < s) steps[i] = s;
+        }
+    }
+    void drop_graphs()
+    {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
+    int graph_for(int k, hipGraphExec_t* out)
+    {
+        auto it = graphs.find(k);
+        if (it != graphs.end()) {
+            *out = it->second;
+            return LBM_OK;
+        }
+        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        int rc = LBM_OK;
+        for (int t = 0; t < k && rc == LBM_OK; ++t) rc = launch_step(t);
+        if (rc == LBM_OK) rc = launch_advance(k);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &g);
+        if (rc != LBM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(LBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        graphs[k] = ex;
+        *out = ex;
+        return LBM_OK;
+    }
+    int macro(int case_id, uint32_t mask, double* fields, bool diag)
+    {
+        const int64_t nb = mtile_count[case_id];
+        if (nb <= 0) return LBM_OK;
+        if (fp64)
+            hipLaunchKernelGGL(k_macro<double>, dim3((unsigned)nb), dim3(256), 0, stream, d_cases(), d_mtiles(),
+                               (int)mtile_begin[case_id], d_steps(), case_id, mask, fields,
+                               diag ? d_partials() : nullptr);
+        else
+            hipLaunchKernelGGL(k_macro<float>, dim3((unsigned)nb), dim3(256), 0, stream, d_cases(), d_mtiles(),
+                               (int)mtile_begin[case_id], d_steps(), case_id, mask, fields,
+                               diag ? d_partials() : nullptr);
+        HIPCHK(hipGetLastError());
+        if (diag) {
+            hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, stream, d_partials(), (int)nb, d_diag());
+            HIPCHK(hipGetLastError());
+        }
+        return LBM_OK;
+    }
+};
+
+#define CHECK_H(h)                                                        \
+    do {                                                                  \
+        if (!(h)) return fail(LBM_E_INVAL, "null handle");                \
+    } while (0)
+#define CHECK_CASE(h, i)                                                                   \
+    do {                                                                                   \
+        if ((i) < 0 || (i) >= (h)->ncases) return fail(LBM_E_INVAL, "case_id %d out of range", (int)(i)); \
+    } while (0)
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err; }
+
+size_t lbm_workspace_bytes(const lbm_case* cases, int32_t ncases)
+{
+    if (!cases || ncases <= 0) return 0;
+    return layout_of(cases, ncases).total;
+}
+
+int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t bytes, void* stream, lbm_handle** out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(LBM_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!cases || ncases <= 0) return fail(LBM_E_INVAL, "no cases");
+    if (!workspace) return fail(LBM_E_INVAL, "workspace is null");
+    if (((uintptr_t)workspace & 255) != 0) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
+    bool any64 = false, any32 = false;
+    for (int i = 0; i < ncases; ++i) {
+        const int rc = validate(cases[i], i);
+        if (rc != LBM_OK) return rc;
+        (cases[i].precision == LBM_FP64 ? any64 : any32) = true;
+    }
+    if (any64 && any32) return fail(LBM_E_INVAL, "FP64 cases cannot share a handle with FP32/FP16S cases");
+    const Layout L = layout_of(cases, ncases);
+    if (bytes < L.total) return fail(LBM_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, L.total);
+
+    lbm_handle* h = new (std::nothrow) lbm_handle();
+    if (!h) return fail(LBM_E_NOMEM, "host allocation failed");
+    h->ncases = ncases;
+    h->cases.assign(cases, cases + ncases);
+    h->stream = (hipStream_t)stream;
+    h->ws = (char*)workspace;
+    h->L = L;
+    h->fp64 = any64;
+    h->steps.assign(ncases, 0);
+    h->shape = shape_ok(1, h->fp64) ? 1 : 0;
+
+    size_t o = L.off_pops;
+    for (int i = 0; i < ncases; ++i) {
+        const size_t b = case_pop_bytes(cases[i]);
+        h->dev.push_back(make_dev(cases[i], h->ws + o, h->ws + o + b));
+        o += 2 * b;
+    }
+    std::vector<TileRec> tiles;
+    auto upload = [&](TileRec* dst) -> int {
+        if (tiles.empty()) return LBM_OK;
+        HIPCHK(hipMemcpyAsync(dst, tiles.data(), tiles.size() * sizeof(TileRec), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return LBM_OK;
+    };
+    int rc = LBM_OK;
+    for (int s = 0; s < kNumShapes && rc == LBM_OK; ++s) {
+        tiles.clear();
+        for (int i = 0; i < ncases; ++i)
+            for (int y = 0; y < cases[i].ny; y += kShapes[s].by)
+                for (int x = 0; x < cases[i].nx; x += kShapes[s].bx) tiles.push_back(TileRec{i, x, y, 0});
+        rc = upload(h->d_tiles(s));
+    }
+    if (rc == LBM_OK) {
+        tiles.clear();
+        for (int i = 0; i < ncases; ++i) {
+            h->mtile_begin.push_back((int64_t)tiles.size());
+            for (int y = 0; y < cases[i].ny; y += kMacroBY)
+                for (int x = 0; x < cases[i].nx; x += kMacroBX) tiles.push_back(TileRec{i, x, y, 0});
+            h->mtile_count.push_back((int64_t)tiles.size() - h->mtile_begin.back());
+        }
+        rc = upload(h->d_mtiles());
+    }
+    if (rc == LBM_OK) {
+        hipError_t e = hipMemcpyAsync(h->d_cases(), h->dev.data(), sizeof(CaseDev) * ncases, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(h->d_steps(), 0, sizeof(int64_t) * ncases, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "upload: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < ncases && rc == LBM_OK; ++i) {
+        hipLaunchKernelGGL(k_init, dim3((cases[i].nx + 255) / 256, cases[i].ny), dim3(256), 0, h->stream, h->d_cases(),
+                           i, make_init(cases[i]), 0, (const double*)nullptr, (const double*)nullptr,
+                           (const double*)nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "k_init: %s", hipGetErrorString(e));
+    }
+    if (rc == LBM_OK) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "init: %s", hipGetErrorString(e));
+    }
+    if (rc != LBM_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t nsteps)
+{
+    CHECK_H(h);
+    if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
+    if (nsteps == 0) return LBM_OK;
+    if (h->timing) {
+        for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+        h->ev.clear();
+        h->timed = 0;
+        for (int64_t t = 0; t < nsteps; ++t) {
+            hipEvent_t a, b;
+            HIPCHK(hipEventCreate(&a));
+            HIPCHK(hipEventCreate(&b));
+            h->ev.push_back(a);
+            h->ev.push_back(b);
+            HIPCHK(hipEventRecord(a, h->stream));
+            int rc = h->launch_step(0);
+            if (rc != LBM_OK) return rc;
+            HIPCHK(hipEventRecord(b, h->stream));
+            rc = h->launch_advance(1);
+            if (rc != LBM_OK) return rc;
+            h->host_advance(1);
+        }
+        h->timed = nsteps;
+        return LBM_OK;
+    }
+    const int64_t CH = 100;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int k = (int)std::min(left, CH);
+        if (h->use_graph) {
+            hipGraphExec_t g = nullptr;
+            int rc = h->graph_for(k, &g);
+            if (rc != LBM_OK) return rc;
+            HIPCHK(hipGraphLaunch(g, h->stream));
+        } else {
+            for (int t = 0; t < k; ++t) {
+                int rc = h->launch_step(t);
+                if (rc != LBM_OK) return rc;
+            }
+            int rc = h->launch_advance(k);
+            if (rc != LBM_OK) return rc;
+        }
+        h->host_advance(k);
+        left -= k;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, int32_t case_id, uint32_t mask, void* dst, int32_t dst_on_device)
+{
+    CHECK_H(h);
+    CHECK_CASE(h, case_id);
+    if (!dst) return fail(LBM_E_INVAL, "dst is null");
+    mask &= LBM_F_ALL;
+    if (!mask) return LBM_OK;
+    const lbm_case& c = h->cases[case_id];
+    const size_t nf = (size_t)__builtin_popcount(mask), bytes = nf * (size_t)c.nx * c.ny * sizeof(double);
+    double* d = (double*)dst;
+    if (!dst_on_device) HIPCHK(hipMalloc(&d, bytes));
+    int rc = h->macro(case_id, mask, d, false);
+    if (!dst_on_device) {
+        hipError_t e = hipSuccess;
+        if (rc == LBM_OK) e = hipMemcpyAsync(dst, d, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        (void)hipFree(d);
+        if (rc == LBM_OK && e != hipSuccess) rc = fail(LBM_E_DEVICE, "lbm_moments copy: %s", hipGetErrorString(e));
+    }
+    return rc;
+}
+
+static int pops_io(lbm_handle* h, int case_id, double* out, const double* in, int on_device)
+{
+    const lbm_case& c = h->cases[case_id];
+    const size_t bytes = (size_t)36 * c.nx * c.ny * sizeof(double);
+    double* d = on_device ? (out ? out : (double*)in) : nullptr;
+    if (!on_device) {
+        HIPCHK(hipMalloc(&d, bytes));
+        if (in) {
+            hipError_t e = hipMemcpyAsync(d, in, bytes, hipMemcpyHostToDevice, h->stream);
+            if (e != hipSuccess) {
+                (void)hipFree(d);
+                return fail(LBM_E_DEVICE, "population upload: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    const int b = (int)(h->steps[case_id] & 1);
+    hipLaunchKernelGGL(k_pops, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id, b,
+                       out ? d : (double*)nullptr, in ? (const double*)d : (const double*)nullptr);
+    hipError_t e = hipGetLastError();
+    if (!on_device) {
+        if (e == hipSuccess && out) e = hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        (void)hipFree(d);
+    }
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, "populations: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle* h, int32_t case_id, void* dst, int32_t dst_on_device)
+{
+    CHECK_H(h);
+    CHECK_CASE(h, case_id);
+    if (!dst) return fail(LBM_E_INVAL, "dst is null");
+    return pops_io(h, case_id, (double*)dst, nullptr, dst_on_device);
+}
+
+int lbm_set_populations(lbm_handle* h, int32_t case_id, const void* src, int32_t src_on_device)
+{
+    CHECK_H(h);
+    CHECK_CASE(h, case_id);
+    if (!src) return fail(LBM_E_INVAL, "src is null");
+    return pops_io(h, case_id, nullptr, (const double*)src, src_on_device);
+}
+
+int lbm_load_fields(lbm_handle* h, int32_t case_id, const void* phi, const void* T, const void* psi,
+                    int32_t src_on_device)
+{
+    CHECK_H(h);
+    CHECK_CASE(h, case_id);
+    if (!phi || !T || !psi) return fail(LBM_E_INVAL, "null field pointer");
+    const lbm_case& c = h->cases[case_id];
+    const size_t n = (size_t)c.nx * c.ny, bytes = n * sizeof(double);
+    const double *dp = (const double*)phi, *dT = (const double*)T, *dq = (const double*)psi;
+    double* tmp = nullptr;
+    if (!src_on_device) {
+        HIPCHK(hipMalloc(&tmp, 3 * bytes));
+        hipError_t e = hipMemcpyAsync(tmp, phi, bytes, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp + n, T, bytes, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp + 2 * n, psi, bytes, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return fail(LBM_E_DEVICE, "field upload: %s", hipGetErrorString(e));
+        }
+        dp = tmp;
+        dT = tmp + n;
+        dq = tmp + 2 * n;
+    }
+    // step counter back to 0 on both sides; state lives in buffer 0
+    h->steps[case_id] = 0;
+    hipError_t e = hipMemsetAsync(h->d_steps() + case_id, 0, sizeof(int64_t), h->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_init, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id,
+                           make_init(c), 0, dp, dT, dq);
+        e = hipGetLastError();
+    }
+    if (tmp) {
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        (void)hipFree(tmp);
+    }
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, "lbm_load_fields: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out)
+{
+    CHECK_H(h);
+    CHECK_CASE(h, case_id);
+    if (!out) return fail(LBM_E_INVAL, "out is null");
+    int rc = h->macro(case_id, 0u, nullptr, true);
+    if (rc != LBM_OK) return rc;
+    double d[NDIAG_PART];
+    HIPCHK(hipMemcpyAsync(d, h->d_diag(), sizeof d, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    out->mass_phi = d[0];
+    out->mass_psi = d[1];
+    out->xc = d[2] / d[0];
+    out->yc = d[3] / d[0];
+    out->ux = d[4] / d[0];
+    out->uy = d[5] / d[0];
+    out->p_in = d[7] > 0 ? d[6] / d[7] : 0.0;
+    out->p_out = d[9] > 0 ? d[8] / d[9] : 0.0;
+    out->nonfinite = d[10];
+    out->phi_min = d[11];
+    out->phi_max = d[12];
+    out->psi_min = d[13];
+    out->psi_max = d[14];
+    out->step = h->steps[case_id];
+    if (d[10] > 0) return fail(LBM_E_NONFINITE, "case %d: %.0f non-finite populations", case_id, d[10]);
+    return LBM_OK;
+}
+
+int lbm_tile_count(void) { return kNumShapes; }
+
+int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by)
+{
+    if (index < 0 || index >= kNumShapes) return fail(LBM_E_INVAL, "tile index %d out of range", index);
+    if (bx) *bx = kShapes[index].bx;
+    if (by) *by = kShapes[index].by;
+    return LBM_OK;
+}
+
+int lbm_set_tile(lbm_handle* h, int32_t index)
+{
+    CHECK_H(h);
+    if (index < 0 || index >= kNumShapes) return fail(LBM_E_INVAL, "tile index %d out of range", index);
+    if (!shape_ok(index, h->fp64)) return fail(LBM_E_INVAL, "tile %d exceeds the LDS budget for FP64", index);
+    if (index != h->shape) h->drop_graphs();
+    h->shape = index;
+    return LBM_OK;
+}
+
+int lbm_get_tile(lbm_handle* h)
+{
+    CHECK_H(h);
+    return h->shape;
+}
+
+int lbm_autotune(lbm_handle* h, int32_t trial_steps)
+{
+    CHECK_H(h);
+    if (trial_steps <= 0) return fail(LBM_E_INVAL, "trial_steps must be > 0");
+    const int keep = h->shape;
+    int best = keep;
+    float best_ms = 1e30f;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    int rc = LBM_OK;
+    for (int s = 0; s < kNumShapes && rc == LBM_OK; ++s) {
+        if (!shape_ok(s, h->fp64)) continue;
+        h->shape = s;
+        // t = 0 every time: each trial re-reads the current state and rewrites
+        // the scratch half of the ping-pong pair, leaving the state unchanged.
+        for (int w = 0; w < 2 && rc == LBM_OK; ++w) rc = h->launch_step(0);
+        if (rc != LBM_OK) break;
+        if (hipEventRecord(a, h->stream) != hipSuccess) { rc = fail(LBM_E_DEVICE, "event"); break; }
+        for (int t = 0; t < trial_steps && rc == LBM_OK; ++t) rc = h->launch_step(0);
+        if (rc != LBM_OK) break;
+        if (hipEventRecord(b, h->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+            rc = fail(LBM_E_DEVICE, "event");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    h->shape = keep;
+    if (rc != LBM_OK) return rc;
+    return lbm_set_tile(h, best);
+}
+
+int lbm_set_graph(lbm_handle* h, int32_t enable)
+{
+    CHECK_H(h);
+    h->use_graph = enable != 0;
+    return LBM_OK;
+}
+
+int64_t lbm_steps_done(lbm_handle* h, int32_t case_id)
+{
+    if (!h || case_id < 0 || case_id >= h->ncases) return -1;
+    return h->steps[case_id];
+}
+
+int lbm_set_kernel_timing(lbm_handle* h, int32_t enable)
+{
+    CHECK_H(h);
+    h->timing = enable != 0;
+    return LBM_OK;
+}
+
+int lbm_kernel_time_ms(lbm_handle* h, double* avg_ms, int64_t* launches)
+{
+    CHECK_H(h);
+    if (h->timed <= 0) return fail(LBM_E_STATE, "no timed lbm_step call");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double tot = 0;
+    for (int64_t i = 0; i < h->timed; ++i) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+        tot += ms;
+    }
+    if (avg_ms) *avg_ms = tot / (double)h->timed;
+    if (launches) *launches = h->timed;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle* h)
+{
+    if (!h) return LBM_OK;
+    (void)hipStreamSynchronize(h->stream);
+    h->drop_graphs();
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -158,7 +158,10 @@ void orc_collide_ad(const double pop[9], double X, double jx, double jy, double 
 
 /* ------------------------------------------------- two-fluid collision */
 /* Equilibrium central moments of the pressure-based scheme (App. C), with
- * varphi = p - rho cs2. */
+ * varphi = p - rho cs2.  The 22 moment, printed as
+ * cs2^3 rho + varphi (ux^2 + cs2)(uy^2 + cs2), is evaluated in the equal form
+ * p cs2^2 + varphi (cs2 (ux^2 + uy^2) + ux^2 uy^2): the printed one cancels two
+ * O(rho/27) terms down to O(p/9) and loses ~12 digits of p. */
 void orc_eq_g(double p, double rho, double ux, double uy, double eq[9])
 {
     const double vp = p - rho * CS2;
@@ -170,7 +173,7 @@ void orc_eq_g(double p, double rho, double ux, double uy, double eq[9])
     eq[5] = vp * ux * uy;
     eq[6] = -vp * (ux * ux + CS2) * uy;
     eq[7] = -vp * (uy * uy + CS2) * ux;
-    eq[8] = CS2 * CS2 * CS2 * rho + vp * (ux * ux + CS2) * (uy * uy + CS2);
+    eq[8] = p * CS2 * CS2 + vp * (CS2 * (ux * ux + uy * uy) + ux * ux * uy * uy);
 }
 
 /* Central moments of the source (App. C); Gamma00 = Fp . u.  Third- and
@@ -449,14 +452,20 @@ static void extend(const orc_state* s, const double* X, double* XE, int kind, in
 }
 
 /* Isotropic finite difference (the stencil the paper takes from Kumar 2004):
- *   d_a X(x) = (1/cs2) sum_alpha w_alpha e_alpha,a X(x + e_alpha). */
+ *   d_a X(x) = (1/cs2) sum_alpha w_alpha e_alpha,a X(x + e_alpha),
+ * evaluated in the equivalent difference form
+ *   (1/cs2) sum_alpha w_alpha e_alpha,a [X(x + e_alpha) - X(x)]
+ * (sum_alpha w_alpha e_alpha = 0), which keeps its accuracy where the gradient
+ * is small against X itself (bubble centres, bulk): the differences of nearby
+ * values are exact, the weighted sum of O(X) terms is not. */
 static void iso_grad_ext(const orc_state* s, const double* XE, int i, int j, double* gx, double* gy)
 {
+    const double X0 = XE[eidx(s, i, j)];
     double ax = 0.0, ay = 0.0;
     for (int a = 1; a < 9; ++a) {
-        const double v = XE[eidx(s, i + EX[a], j + EY[a])];
-        ax += WT[a] * EX[a] * v;
-        ay += WT[a] * EY[a] * v;
+        const double d = XE[eidx(s, i + EX[a], j + EY[a])] - X0;
+        ax += WT[a] * EX[a] * d;
+        ay += WT[a] * EY[a] * d;
     }
     *gx = ax / CS2;
     *gy = ay / CS2;
@@ -467,9 +476,10 @@ void orc_grad_periodic(const double* X, int32_t nx, int32_t ny, double* gx, doub
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double ax = 0.0, ay = 0.0;
+            const double X0 = X[(size_t)j * nx + i];
             for (int a = 1; a < 9; ++a) {
                 const int ii = ((i + EX[a]) % nx + nx) % nx, jj = ((j + EY[a]) % ny + ny) % ny;
-                const double v = X[(size_t)jj * nx + ii];
+                const double v = X[(size_t)jj * nx + ii] - X0;
                 ax += WT[a] * EX[a] * v;
                 ay += WT[a] * EY[a] * v;
             }
@@ -569,7 +579,7 @@ static void macro_stage(orc_state* s)
             double kap = 0.0;
             for (int a = 1; a < 9; ++a) {
                 const size_t en = eidx(s, i + EX[a], j + EY[a]);
-                kap += WT[a] * (EX[a] * s->nxE[en] + EY[a] * s->nyE[en]);
+                kap += WT[a] * (EX[a] * (s->nxE[en] - nxv) + EY[a] * (s->nyE[en] - nyv));
             }
             kap /= CS2;
 

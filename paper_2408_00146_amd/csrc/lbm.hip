@@ -166,84 +166,132 @@ struct InitDev {
     uint64_t seed;
 };
 
-// Rest-equilibrium populations X_a = w_a X of given phi, T, psi (g = 0 for
-// p = 0, u = 0), encoded into buffer `b` of the case.  Null field pointers
-// select the built-in initial condition (tanh interface (Sec. 3) + noise,
-// linear wall law for T, psi band).
-template <typename S, typename R>
-__device__ void init_node(const CaseDev& cd, const InitDev& in, int b, int x, int y, const double* phi_in,
-                          const double* T_in, const double* psi_in)
-{
-    const int64_t k = (int64_t)y * cd.nx + x;
-    double phi, T, psi;
-    if (phi_in) {
-        phi = phi_in[k];
-        T = T_in[k];
-        psi = psi_in[k];
-    } else {
-        double d = 0.0, pc = 0.0;
-        if (in.kind != 2) {
-            if (in.kind == 1) d = in.R - fabs((double)y - in.yc);
-            else d = in.R - sqrt(((double)x - in.xc) * ((double)x - in.xc) + ((double)y - in.yc) * ((double)y - in.yc));
-            pc = 0.5 + 0.5 * tanh(2.0 * d / in.W);
-        }
-        phi = pc + in.phi_noise * noise_unit(in.seed, (uint64_t)k);
-        T = cd.T0 + cd.gradT * ((double)x - cd.xT0);
-        psi = in.psi_bulk + in.psi_band * 4.0 * pc * (1.0 - pc);
-    }
-    const double Tr = cd.refs ? cd.T0 + cd.gradT * ((double)x - cd.xT0) : 0.0;
-    const double qr = cd.refs ? cd.ref_q : 0.0;
-    S* buf = (S*)cd.buf[b];
-    const int64_t o = (int64_t)y * cd.pitch + x;
-    const R sc = R(cd.scale);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const double w = wt(a);
-        buf[(int64_t)(SET_F * 9 + a) * cd.plane + o] = enc<S, R>(R(w * phi), sc);
-        buf[(int64_t)(SET_G * 9 + a) * cd.plane + o] = enc<S, R>(R(0), sc);
-        buf[(int64_t)(SET_H * 9 + a) * cd.plane + o] = enc<S, R>(R(w * (T - Tr)), sc);
-        buf[(int64_t)(SET_Q * 9 + a) * cd.plane + o] = enc<S, R>(R(w * (psi - qr)), sc);
-    }
-}
+// Where the post-streaming state of a case comes from: FP64 population
+// planes [4][9][ny][nx], or FP64 fields phi/T/psi (rest equilibrium,
+// g = 0 for p = 0, u = 0), or the built-in initial condition (tanh
+// interface of Sec. 3 plus noise, linear wall law for T, psi band).
+struct StateSrc {
+    const double* pops;
+    const double *phi, *T, *psi;
+    InitDev in;
+};
 
-__global__ void k_init(const CaseDev* __restrict__ cases, int case_id, InitDev in, int b, const double* phi_in,
-                       const double* T_in, const double* psi_in)
-{
-    const CaseDev& cd = cases[case_id];
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= cd.nx || y >= cd.ny) return;
-    if (cd.prec == PREC_FP64) init_node<double, double>(cd, in, b, x, y, phi_in, T_in, psi_in);
-    else if (cd.prec == PREC_FP16S) init_node<__half, float>(cd, in, b, x, y, phi_in, T_in, psi_in);
-    else init_node<float, float>(cd, in, b, x, y, phi_in, T_in, psi_in);
-}
-
-// Populations <-> FP64 planes [4][9][ny][nx] (full values, references added).
-template <typename S, typename R>
-__device__ void pops_node(const CaseDev& cd, int b, int x, int y, double* out, const double* in)
+__device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, int x, int y)
 {
     const int64_t n = (int64_t)cd.nx * cd.ny, k = (int64_t)y * cd.nx + x;
-    const double ref[4] = {0.0, 0.0, cd.refs ? cd.T0 + cd.gradT * ((double)x - cd.xT0) : 0.0,
-                           cd.refs ? cd.ref_q : 0.0};
-    S* buf = (S*)cd.buf[b];
-    const int64_t o = (int64_t)y * cd.pitch + x;
-    for (int set = 0; set < 4; ++set)
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int64_t i = (int64_t)(set * 9 + a) * cd.plane + o;
-            const int64_t j = (int64_t)(set * 9 + a) * n + k;
-            if (out) out[j] = (double)dec<S, R>(buf[i], R(cd.inv_scale)) + wt(a) * ref[set];
-            else buf[i] = enc<S, R>(R(in[j] - wt(a) * ref[set]), R(cd.scale));
+    if (s.pops) return s.pops[(int64_t)(set * 9 + a) * n + k];
+    if (set == SET_G) return 0.0;
+    double X;
+    if (s.phi) {
+        X = set == SET_F ? s.phi[k] : (set == SET_H ? s.T[k] : s.psi[k]);
+    } else if (set == SET_H) {
+        X = cd.T0 + cd.gradT * ((double)x - cd.xT0);
+    } else {
+        double pc = 0.0;
+        if (s.in.kind != 2) {
+            double d;
+            if (s.in.kind == 1) d = s.in.R - fabs((double)y - s.in.yc);
+            else d = s.in.R - sqrt(((double)x - s.in.xc) * ((double)x - s.in.xc) + ((double)y - s.in.yc) * ((double)y - s.in.yc));
+            pc = 0.5 + 0.5 * tanh(2.0 * d / s.in.W);
         }
+        X = set == SET_F ? pc + s.in.phi_noise * noise_unit(s.in.seed, (uint64_t)k)
+                         : s.in.psi_bulk + s.in.psi_band * 4.0 * pc * (1.0 - pc);
+    }
+    return wt(a) * X;
 }
 
-__global__ void k_pops(const CaseDev* __restrict__ cases, int case_id, int b, double* out, const double* in)
+__device__ __forceinline__ double ref_of(const CaseDev& cd, int set, int x)
+{
+    if (!cd.refs) return 0.0;
+    if (set == SET_H) return cd.T0 + cd.gradT * ((double)x - cd.xT0);
+    if (set == SET_Q) return cd.ref_q;
+    return 0.0;
+}
+
+// Store a post-streaming state into buffer `b` as the post-collision values
+// that the pull of the next step streams into it (inverse streaming).  Slot
+// (a, y) feeds node t = y + e_a; if t lies beyond a wall the slot is read
+// back by y itself through the wall rule of direction abar, so its value is
+// the inverse of that bounce-back / anti-bounce-back.  Deviation storage is
+// relative to the reference of the slot's own column.
+template <typename S, typename R>
+__device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x, int y0y)
+{
+    S* buf = (S*)cd.buf[b];
+    const int64_t o = (int64_t)y0y * cd.pitch + y0x;
+    const R sc = R(cd.scale);
+    for (int set = 0; set < 4; ++set) {
+        const double ry = ref_of(cd, set, y0x);
+        for (int a = 0; a < 9; ++a) {
+            const double w = wt(a);
+            int tx = y0x + ex(a), ty = y0y + ey(a);
+            if (!cd.wallx) tx = tx < 0 ? tx + cd.nx : (tx >= cd.nx ? tx - cd.nx : tx);
+            if (!cd.wally) ty = ty < 0 ? ty + cd.ny : (ty >= cd.ny ? ty - cd.ny : ty);
+            const bool outy = ty < 0 || ty >= cd.ny, outx = tx < 0 || tx >= cd.nx;
+            double v;
+            if (!outx && !outy) {
+                v = src_pop(cd, s, set, a, tx, ty) - w * ry;
+            } else {
+                const int side = outy ? (ty < 0 ? 2 : 3) : (tx < 0 ? 0 : 1);
+                const double dev_b = src_pop(cd, s, set, opp(a), y0x, y0y) - w * ry;
+                if (set == SET_H && cd.tbc[side]) {
+                    const double d = cd.refs ? 0.5 * cd.gradT * ex(a)
+                                             : cd.T0 + cd.gradT * ((double)y0x + 0.5 * ex(a) - cd.xT0);
+                    v = 2.0 * w * d - dev_b;
+                } else if (set == SET_Q && cd.pbc[side]) {
+                    v = 2.0 * w * (cd.psi_w[side] - (cd.refs ? cd.ref_q : 0.0)) - dev_b;
+                } else {
+                    v = dev_b;
+                }
+            }
+            buf[(int64_t)(set * 9 + a) * cd.plane + o] = enc<S, R>(R(v), sc);
+        }
+    }
+}
+
+__global__ void k_store(const CaseDev* __restrict__ cases, int case_id, StateSrc src, int b)
 {
     const CaseDev& cd = cases[case_id];
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= cd.nx || y >= cd.ny) return;
-    if (cd.prec == PREC_FP64) pops_node<double, double>(cd, b, x, y, out, in);
-    else if (cd.prec == PREC_FP16S) pops_node<__half, float>(cd, b, x, y, out, in);
-    else pops_node<float, float>(cd, b, x, y, out, in);
+    if (cd.prec == PREC_FP64) store_node<double, double>(cd, src, b, x, y);
+    else if (cd.prec == PREC_FP16S) store_node<__half, float>(cd, src, b, x, y);
+    else store_node<float, float>(cd, src, b, x, y);
+}
+
+// Post-streaming populations of the current state as FP64 planes
+// [4][9][ny][nx] (full values): the same pull the step performs.
+template <int SET, typename S, typename R>
+__device__ __forceinline__ void export_set(const Ctx<R>& c, const S* src, int x, int y, double* out, int64_t n, R ref)
+{
+    R v[9];
+    pull9<SET>(c, src, x, y, v);
+    const int64_t k = (int64_t)y * c.nx + x;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[(int64_t)(SET * 9 + a) * n + k] = (double)v[a] + wt(a) * (double)ref;
+}
+
+template <typename S, typename R>
+__device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
+{
+    Ctx<R> c;
+    c.load(cd);
+    const S* src = (const S*)cd.buf[b];
+    const int64_t n = (int64_t)cd.nx * cd.ny;
+    export_set<SET_F>(c, src, x, y, out, n, R(0));
+    export_set<SET_G>(c, src, x, y, out, n, R(0));
+    export_set<SET_H>(c, src, x, y, out, n, c.Tref_x(x));
+    export_set<SET_Q>(c, src, x, y, out, n, c.qref());
+}
+
+__global__ void k_export(const CaseDev* __restrict__ cases, int case_id, int b, double* out)
+{
+    const CaseDev& cd = cases[case_id];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= cd.nx || y >= cd.ny) return;
+    if (cd.prec == PREC_FP64) export_node<double, double>(cd, b, x, y, out);
+    else if (cd.prec == PREC_FP16S) export_node<__half, float>(cd, b, x, y, out);
+    else export_node<float, float>(cd, b, x, y, out);
 }
 
 }  // namespace lbm
@@ -621,11 +669,12 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "upload: %s", hipGetErrorString(e));
     }
     for (int i = 0; i < ncases && rc == LBM_OK; ++i) {
-        hipLaunchKernelGGL(k_init, dim3((cases[i].nx + 255) / 256, cases[i].ny), dim3(256), 0, h->stream, h->d_cases(),
-                           i, make_init(cases[i]), 0, (const double*)nullptr, (const double*)nullptr,
-                           (const double*)nullptr);
+        StateSrc src{};
+        src.in = make_init(cases[i]);
+        hipLaunchKernelGGL(k_store, dim3((cases[i].nx + 255) / 256, cases[i].ny), dim3(256), 0, h->stream, h->d_cases(),
+                           i, src, 0);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "k_init: %s", hipGetErrorString(e));
+        if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "k_store: %s", hipGetErrorString(e));
     }
     if (rc == LBM_OK) {
         hipError_t e = hipStreamSynchronize(h->stream);
@@ -726,8 +775,15 @@ static int pops_io(lbm_handle* h, int case_id, double* out, const double* in, in
         }
     }
     const int b = (int)(h->steps[case_id] & 1);
-    hipLaunchKernelGGL(k_pops, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id, b,
-                       out ? d : (double*)nullptr, in ? (const double*)d : (const double*)nullptr);
+    if (out) {
+        hipLaunchKernelGGL(k_export, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id,
+                           b, d);
+    } else {
+        StateSrc src{};
+        src.pops = d;
+        hipLaunchKernelGGL(k_store, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id,
+                           src, b);
+    }
     hipError_t e = hipGetLastError();
     if (!on_device) {
         if (e == hipSuccess && out) e = hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, h->stream);
@@ -781,8 +837,12 @@ int lbm_load_fields(lbm_handle* h, int32_t case_id, const void* phi, const void*
     h->steps[case_id] = 0;
     hipError_t e = hipMemsetAsync(h->d_steps() + case_id, 0, sizeof(int64_t), h->stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_init, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id,
-                           make_init(c), 0, dp, dT, dq);
+        StateSrc src{};
+        src.phi = dp;
+        src.T = dT;
+        src.psi = dq;
+        hipLaunchKernelGGL(k_store, dim3((c.nx + 255) / 256, c.ny), dim3(256), 0, h->stream, h->d_cases(), case_id,
+                           src, 0);
         e = hipGetLastError();
     }
     if (tmp) {

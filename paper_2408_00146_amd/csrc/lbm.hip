@@ -33,11 +33,31 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// A tile whose 3-node halo lies inside the lattice needs no wrap or wall logic.
+__device__ __forceinline__ bool interior(const CaseDev& cd, int x0, int y0, int bx, int by)
+{
+    return x0 >= 3 && y0 >= 3 && x0 + bx + 3 <= cd.nx && y0 + by + 3 <= cd.ny;
+}
+
+template <typename R, typename S, int BX, int BY, int MODE>
+__device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int x0, int y0, int b, Smem<R, BX, BY, sizeof(R) == 4>& sh,
+                                         const MacroOut& mo, double* dacc)
+{
+    const S* src = (const S*)cd.buf[b];
+    S* dst = MODE == MODE_STEP ? (S*)cd.buf[b ^ 1] : nullptr;
+    const __half* rsrc = cd.rbuf[b];
+    __half* rdst = MODE == MODE_STEP ? cd.rbuf[b ^ 1] : nullptr;
+    if (interior(cd, x0, y0, BX, BY))
+        tile_body<R, S, BX, BY, MODE, true>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
+    else
+        tile_body<R, S, BX, BY, MODE, false>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
+}
+
 template <typename R, int BX, int BY>
 __global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
                                               int ntiles, const int64_t* __restrict__ steps, int t)
 {
-    __shared__ Smem<R, BX, BY> sh;
+    __shared__ Smem<R, BX, BY, sizeof(R) == 4> sh;
     const TileRec tr = tiles[xcd_remap(blockIdx.x, ntiles)];
     const CaseDev& cd = cases[tr.c];
     const int64_t s = steps[tr.c] + t;
@@ -45,16 +65,12 @@ __global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases,
     Ctx<R> c;
     c.load(cd);
     const MacroOut mo{nullptr, 0u, nullptr};
+    const int b = (int)(s & 1);
     if constexpr (sizeof(R) == 8) {
-        tile_body<double, double, BX, BY, MODE_STEP>(c, tr.x0, tr.y0, (const double*)cd.buf[s & 1],
-                                                     (double*)cd.buf[(s + 1) & 1], sh, mo, nullptr);
+        run_tile<double, double, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
     } else {
-        if (cd.prec == PREC_FP16S)
-            tile_body<float, __half, BX, BY, MODE_STEP>(c, tr.x0, tr.y0, (const __half*)cd.buf[s & 1],
-                                                        (__half*)cd.buf[(s + 1) & 1], sh, mo, nullptr);
-        else
-            tile_body<float, float, BX, BY, MODE_STEP>(c, tr.x0, tr.y0, (const float*)cd.buf[s & 1],
-                                                       (float*)cd.buf[(s + 1) & 1], sh, mo, nullptr);
+        if (cd.prec == PREC_FP16S) run_tile<float, __half, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+        else run_tile<float, float, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
     }
 }
 
@@ -104,11 +120,11 @@ __global__ __launch_bounds__(256) void k_macro(const CaseDev* __restrict__ cases
                                                int tile0, const int64_t* __restrict__ steps, int case_id,
                                                uint32_t mask, double* fields, double* partials)
 {
-    __shared__ Smem<R, kMacroBX, kMacroBY> sh;
+    __shared__ Smem<R, kMacroBX, kMacroBY, sizeof(R) == 4> sh;
     __shared__ double red[4][NDIAG_PART];
     const TileRec tr = tiles[tile0 + blockIdx.x];
     const CaseDev& cd = cases[case_id];
-    const int64_t s = steps[case_id];
+    const int b = (int)(steps[case_id] & 1);
     Ctx<R> c;
     c.load(cd);
     const MacroOut mo{fields, mask, partials};
@@ -116,15 +132,12 @@ __global__ __launch_bounds__(256) void k_macro(const CaseDev* __restrict__ cases
     diag_init(acc);
     double* dacc = partials ? acc : nullptr;
     if constexpr (sizeof(R) == 8) {
-        tile_body<double, double, kMacroBX, kMacroBY, MODE_MACRO>(c, tr.x0, tr.y0, (const double*)cd.buf[s & 1],
-                                                                  nullptr, sh, mo, dacc);
+        run_tile<double, double, kMacroBX, kMacroBY, MODE_MACRO>(cd, c, tr.x0, tr.y0, b, sh, mo, dacc);
     } else {
         if (cd.prec == PREC_FP16S)
-            tile_body<float, __half, kMacroBX, kMacroBY, MODE_MACRO>(c, tr.x0, tr.y0, (const __half*)cd.buf[s & 1],
-                                                                     nullptr, sh, mo, dacc);
+            run_tile<float, __half, kMacroBX, kMacroBY, MODE_MACRO>(cd, c, tr.x0, tr.y0, b, sh, mo, dacc);
         else
-            tile_body<float, float, kMacroBX, kMacroBY, MODE_MACRO>(c, tr.x0, tr.y0, (const float*)cd.buf[s & 1],
-                                                                    nullptr, sh, mo, dacc);
+            run_tile<float, float, kMacroBX, kMacroBY, MODE_MACRO>(cd, c, tr.x0, tr.y0, b, sh, mo, dacc);
     }
     if (partials) block_reduce(acc, red, partials + (int64_t)blockIdx.x * NDIAG_PART);
 }
@@ -200,28 +213,36 @@ __device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, 
     return wt(a) * X;
 }
 
-__device__ __forceinline__ double ref_of(const CaseDev& cd, int set, int x)
-{
-    if (!cd.refs) return 0.0;
-    if (set == SET_H) return cd.T0 + cd.gradT * ((double)x - cd.xT0);
-    if (set == SET_Q) return cd.ref_q;
-    return 0.0;
-}
-
 // Store a post-streaming state into buffer `b` as the post-collision values
 // that the pull of the next step streams into it (inverse streaming).  Slot
 // (a, y) feeds node t = y + e_a; if t lies beyond a wall the slot is read
 // back by y itself through the wall rule of direction abar, so its value is
-// the inverse of that bounce-back / anti-bounce-back.  Deviation storage is
-// relative to the reference of the slot's own column.
+// the inverse of that bounce-back / anti-bounce-back.  Reduced-precision
+// storage is relative to the slot node's own references: the FP16-rounded
+// phi and psi of the state at y (written to the reference planes), and the
+// linear wall law for h.
 template <typename S, typename R>
 __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x, int y0y)
 {
     S* buf = (S*)cd.buf[b];
     const int64_t o = (int64_t)y0y * cd.pitch + y0x;
     const R sc = R(cd.scale);
+    double ref[4] = {0.0, 0.0, 0.0, 0.0};
+    if (cd.refs) {
+        double sf = 0.0, sq = 0.0;
+        for (int a = 0; a < 9; ++a) {
+            sf += src_pop(cd, s, SET_F, a, y0x, y0y);
+            sq += src_pop(cd, s, SET_Q, a, y0x, y0y);
+        }
+        const __half hf = __float2half_rn((float)sf), hq = __float2half_rn((float)sq);
+        cd.rbuf[b][o] = hf;
+        cd.rbuf[b][cd.plane + o] = hq;
+        ref[SET_F] = (double)__half2float(hf);
+        ref[SET_Q] = (double)__half2float(hq);
+        ref[SET_H] = cd.T0 + cd.gradT * ((double)y0x - cd.xT0);
+    }
     for (int set = 0; set < 4; ++set) {
-        const double ry = ref_of(cd, set, y0x);
+        const double ry = ref[set];
         for (int a = 0; a < 9; ++a) {
             const double w = wt(a);
             int tx = y0x + ex(a), ty = y0y + ey(a);
@@ -235,11 +256,11 @@ __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x,
                 const int side = outy ? (ty < 0 ? 2 : 3) : (tx < 0 ? 0 : 1);
                 const double dev_b = src_pop(cd, s, set, opp(a), y0x, y0y) - w * ry;
                 if (set == SET_H && cd.tbc[side]) {
-                    const double d = cd.refs ? 0.5 * cd.gradT * ex(a)
-                                             : cd.T0 + cd.gradT * ((double)y0x + 0.5 * ex(a) - cd.xT0);
+                    const double Tw = cd.T0 + cd.gradT * ((double)y0x + 0.5 * ex(a) - cd.xT0);
+                    const double d = cd.refs ? 0.5 * cd.gradT * ex(a) : Tw;  // T_w - reference
                     v = 2.0 * w * d - dev_b;
                 } else if (set == SET_Q && cd.pbc[side]) {
-                    v = 2.0 * w * (cd.psi_w[side] - (cd.refs ? cd.ref_q : 0.0)) - dev_b;
+                    v = 2.0 * w * (cd.psi_w[side] - ry) - dev_b;
                 } else {
                     v = dev_b;
                 }
@@ -260,28 +281,41 @@ __global__ void k_store(const CaseDev* __restrict__ cases, int case_id, StateSrc
 }
 
 // Post-streaming populations of the current state as FP64 planes
-// [4][9][ny][nx] (full values): the same pull the step performs.
-template <int SET, typename S, typename R>
-__device__ __forceinline__ void export_set(const Ctx<R>& c, const S* src, int x, int y, double* out, int64_t n, R ref)
+// [4][9][ny][nx] (full values): the same pull the step performs, with the
+// per-node references read from global memory.
+template <int SET, typename S, typename R, typename RF>
+__device__ __forceinline__ void export_set(const Ctx<R>& c, const S* src, int x, int y, double* out, int64_t n, R base,
+                                           const RF& rf)
 {
+    constexpr bool REFS = sizeof(R) == 4;
     R v[9];
-    pull9<SET>(c, src, x, y, v);
+    pull9<SET, false, REFS>(c, src, x, y, x, y, base, rf, v);
     const int64_t k = (int64_t)y * c.nx + x;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) out[(int64_t)(SET * 9 + a) * n + k] = (double)v[a] + wt(a) * (double)ref;
+    for (int a = 0; a < 9; ++a) out[(int64_t)(SET * 9 + a) * n + k] = (double)v[a] + wt(a) * (double)base;
 }
 
 template <typename S, typename R>
 __device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
 {
+    constexpr bool REFS = sizeof(R) == 4;
     Ctx<R> c;
     c.load(cd);
     const S* src = (const S*)cd.buf[b];
+    const __half* rb = cd.rbuf[b];
     const int64_t n = (int64_t)cd.nx * cd.ny;
-    export_set<SET_F>(c, src, x, y, out, n, R(0));
-    export_set<SET_G>(c, src, x, y, out, n, R(0));
-    export_set<SET_H>(c, src, x, y, out, n, c.Tref_x(x));
-    export_set<SET_Q>(c, src, x, y, out, n, c.qref());
+    auto node = [&](int ux, int uy) -> int64_t {
+        if (!c.wallx) ux = ux < 0 ? ux + c.nx : (ux >= c.nx ? ux - c.nx : ux);
+        if (!c.wally) uy = uy < 0 ? uy + c.ny : (uy >= c.ny ? uy - c.ny : uy);
+        return (int64_t)uy * c.pitch + ux;
+    };
+    auto rf = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[node(ux, uy)])) : R(0); };
+    auto rq = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[c.plane + node(ux, uy)])) : R(0); };
+    auto none = [&](int, int) -> R { return R(0); };
+    export_set<SET_F>(c, src, x, y, out, n, rf(x, y), rf);
+    export_set<SET_G>(c, src, x, y, out, n, R(0), none);
+    export_set<SET_H>(c, src, x, y, out, n, REFS ? c.Tlaw(R(x)) : R(0), none);
+    export_set<SET_Q>(c, src, x, y, out, n, rq(x, y), rq);
 }
 
 __global__ void k_export(const CaseDev* __restrict__ cases, int case_id, int b, double* out)
@@ -326,6 +360,9 @@ int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * pitch_of(c.nx) * c.ny * elem_bytes(c.precision)); }
 
+// Per-node storage references (phi, psi) of reduced-precision cases: 2 FP16 planes per buffer.
+size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)2 * pitch_of(c.nx) * c.ny * 2); }
+
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
 
 struct Layout {
@@ -363,7 +400,7 @@ Layout layout_of(const lbm_case* cs, int n)
     L.off_mtiles = o;
     o = align256(o + sizeof(TileRec) * (size_t)mt);
     L.off_pops = o;
-    for (int i = 0; i < n; ++i) o += 2 * case_pop_bytes(cs[i]);
+    for (int i = 0; i < n; ++i) o += 2 * (case_pop_bytes(cs[i]) + case_ref_bytes(cs[i]));
     L.total = o;
     return L;
 }
@@ -391,7 +428,7 @@ int validate(const lbm_case& c, int i)
     return LBM_OK;
 }
 
-CaseDev make_dev(const lbm_case& c, void* b0, void* b1)
+CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
 {
     CaseDev d{};
     d.nx = c.nx;
@@ -432,13 +469,14 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1)
     d.Fx = c.Fext_x;
     d.Fy = c.Fext_y;
     d.grav = c.gravity;
-    d.ref_q = c.psi_bulk;
     d.scale = c.precision == LBM_FP16S ? 1024.0 : 1.0;
     d.inv_scale = 1.0 / d.scale;
     d.plane = (int64_t)c.ny * d.pitch;
     d.max_steps = c.max_steps;
     d.buf[0] = b0;
     d.buf[1] = b1;
+    d.rbuf[0] = (__half*)r0;
+    d.rbuf[1] = (__half*)r1;
     return d;
 }
 
@@ -473,11 +511,12 @@ StepKernel step_kernel(int shape)
     return nullptr;
 }
 
-// FP64 tiles must fit the 64 KiB per-workgroup LDS budget.
+// Tiles must fit the 64 KiB per-workgroup LDS budget (two workgroups per CU).
 bool shape_ok(int shape, bool fp64)
 {
     const int bx = kShapes[shape].bx, by = kShapes[shape].by;
-    const size_t lds = (size_t)((bx + 4) * (by + 4) + 4 * (bx + 2) * (by + 2)) * (fp64 ? 8 : 4);
+    const size_t e3 = fp64 ? 0 : (size_t)(bx + 6) * (by + 6), e2 = (size_t)(bx + 4) * (by + 4), e1 = (size_t)(bx + 2) * (by + 2);
+    const size_t lds = (2 * e3 + (fp64 ? 1 : 2) * e2 + 5 * e1) * (fp64 ? 8 : 4) + 8 * e1;
     return lds <= 65536;
 }
 
@@ -633,9 +672,10 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
 
     size_t o = L.off_pops;
     for (int i = 0; i < ncases; ++i) {
-        const size_t b = case_pop_bytes(cases[i]);
-        h->dev.push_back(make_dev(cases[i], h->ws + o, h->ws + o + b));
-        o += 2 * b;
+        const size_t b = case_pop_bytes(cases[i]), r = case_ref_bytes(cases[i]);
+        char* base = h->ws + o;
+        h->dev.push_back(make_dev(cases[i], base, base + b, r ? base + 2 * b : nullptr, r ? base + 2 * b + r : nullptr));
+        o += 2 * (b + r);
     }
     std::vector<TileRec> tiles;
     auto upload = [&](TileRec* dst) -> int {

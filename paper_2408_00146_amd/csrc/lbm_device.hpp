@@ -4,15 +4,25 @@
 // coupled through the isotropic-gradient force terms of Sec. 2-3.
 //
 // One workgroup owns one BX x BY tile of one case.  Per time step it
-//   1. pulls (streams) populations from the source buffer for the tile plus a
-//      halo and reduces them to phi (2-node halo), p*, sigma(T, psi) (1-node
-//      halo) in LDS;
-//   2. forms the interface normal on the tile plus 1-node halo in LDS;
+//   0. (reduced precision) stages the per-node storage references of the
+//      tile plus a 3-node halo in LDS;
+//   1. pulls (streams) populations for the tile plus a halo and reduces them
+//      to phi (2-node halo), p*, T, psi (1-node halo) in LDS; halo nodes
+//      beyond a wall are then filled from their mirror nodes;
+//   2. forms the interface normal and sigma(T, psi) on the tile plus 1 halo;
 //   3. per own node: curvature, CSF force, pressure force, velocity,
 //      pressure, the four central-moment collisions, store into the
 //      destination buffer (pull ping-pong: every node writes only itself).
 // Populations are SoA planes [set][dir][y][pitch] so that a wavefront of 64
 // consecutive x reads/writes contiguous memory.
+//
+// Reduced-precision storage (FP32, FP16 x 2^10) keeps each population as a
+// deviation from the rest equilibrium of a per-node reference: for f and q
+// the FP16-rounded phi and psi of the node that wrote it (two extra FP16
+// planes per buffer), for h the linear wall-temperature law, for g zero.
+// Deviations are O(u, grad) small, so FP16/FP32 keep their relative
+// precision on them; phi and psi are carried as reference + deviation until
+// they enter a difference, so gradients stay accurate where phi is ~1.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -35,7 +45,7 @@ enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16S = 2 };
 // Device copy of one case, precomputed on the host.
 struct CaseDev {
     int32_t nx, ny, pitch, prec;
-    int32_t wallx, wally, law, refs;  // refs: populations stored as deviations from w*X_ref
+    int32_t wallx, wally, law, refs;  // refs: reduced-precision deviation storage
     int32_t tbc[4], pbc[4];
     double psi_w[4];
     double T0, gradT, xT0;
@@ -43,10 +53,11 @@ struct CaseDev {
     double rhoA, drho, muA, dmu, alphaA, dalpha;
     double om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     double Fx, Fy, grav;
-    double ref_q, scale, inv_scale;
+    double scale, inv_scale;
     int64_t plane;      // elements per (set, dir) plane = ny * pitch
     int64_t max_steps;  // <= 0: unlimited
     void* buf[2];       // ping-pong population buffers
+    __half* rbuf[2];    // per-node references [2 = phi, psi][ny][pitch] of each buffer (refs only)
 };
 
 struct TileRec {
@@ -56,7 +67,7 @@ struct TileRec {
 // Per-case constants in the compute type, loaded once per tile.
 template <typename R>
 struct Ctx {
-    int nx, ny, pitch, wallx, wally, law, refs;
+    int nx, ny, pitch, wallx, wally, law;
     int tbc, pbc;  // bit s set: Dirichlet T / psi on side s (no dynamic array indexing: keeps Ctx in registers)
     int64_t plane;
     const double* psi_w;  // wall values read from global memory (a select over struct fields would defeat SROA)
@@ -64,11 +75,14 @@ struct Ctx {
     R s0, sT, sTT, Tref, beta, inv_psi_inf;
     R rhoA, drho, muA, dmu, alphaA, dalpha;
     R om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
-    R Fx, Fy, grav, ref_q, scale, inv_scale;
+    R Fx, Fy, grav, scale, inv_scale;
+    // surface tension and the wall-temperature law in FP64 (sigma and its
+    // gradient are formed in FP64 in every precision)
+    double T0d, gradTd, xT0d, s0d, sTd, sTTd, Trefd, betad, ipsid;
 
     __device__ void load(const CaseDev& c)
     {
-        nx = c.nx; ny = c.ny; pitch = c.pitch; wallx = c.wallx; wally = c.wally; law = c.law; refs = c.refs;
+        nx = c.nx; ny = c.ny; pitch = c.pitch; wallx = c.wallx; wally = c.wally; law = c.law;
         plane = c.plane;
         tbc = (c.tbc[0] ? 1 : 0) | (c.tbc[1] ? 2 : 0) | (c.tbc[2] ? 4 : 0) | (c.tbc[3] ? 8 : 0);
         pbc = (c.pbc[0] ? 1 : 0) | (c.pbc[1] ? 2 : 0) | (c.pbc[2] ? 4 : 0) | (c.pbc[3] ? 8 : 0);
@@ -78,16 +92,16 @@ struct Ctx {
         rhoA = R(c.rhoA); drho = R(c.drho); muA = R(c.muA); dmu = R(c.dmu); alphaA = R(c.alphaA); dalpha = R(c.dalpha);
         om_phi = R(c.om_phi); om_psi = R(c.om_psi); Mphi = R(c.Mphi); W = R(c.W); Dpsi = R(c.Dpsi);
         s_lam = R(c.s_lam); w_lam = R(c.w_lam); Fx = R(c.Fx); Fy = R(c.Fy); grav = R(c.grav);
-        ref_q = R(c.ref_q); scale = R(c.scale); inv_scale = R(c.inv_scale);
+        scale = R(c.scale); inv_scale = R(c.inv_scale);
+        T0d = c.T0; gradTd = c.gradT; xT0d = c.xT0; s0d = c.s0; sTd = c.sT; sTTd = c.sTT; Trefd = c.Tref;
+        betad = c.beta; ipsid = c.inv_psi_inf;
     }
     __device__ bool t_dir(int side) const { return (tbc >> side) & 1; }
     __device__ bool p_dir(int side) const { return (pbc >> side) & 1; }
     __device__ R psi_wall(int side) const { return R(psi_w[side]); }
-    // Imposed linear wall-temperature law (also the storage reference of h).
+    // Imposed linear wall-temperature law.
     __device__ R Tlaw(R x) const { return T0 + gradT * (x - xT0); }
-    // Storage reference of h at node column x (0 when populations are raw).
-    __device__ R Tref_x(int x) const { return refs ? Tlaw(R(x)) : R(0); }
-    __device__ R qref() const { return refs ? ref_q : R(0); }
+    __device__ double Tlaw_d(double x) const { return T0d + gradTd * (x - xT0d); }
 };
 
 // ------------------------------------------------------------ storage codec
@@ -110,56 +124,66 @@ template <>
 __device__ __forceinline__ __half enc<__half, float>(float v, float scale) { return __float2half_rn(v * scale); }
 
 // ----------------------------------------------------------- streaming
-// Post-streaming population X_a at node (x, y), as a deviation from the
-// storage reference of node (x, y): X_a(x) = X~_a(x - e_a) (pull).  A source
-// beyond a wall gives halfway bounce-back X_a(x) = X~_abar(x), or for a
-// Dirichlet scalar (h: T_w(x - e_a/2); q: psi_w) the anti-bounce-back
-// X_a(x) = -X~_abar(x) + 2 w_a X_w.  A source beyond both a y-wall and an
-// x-wall follows the y-wall's rule.
-template <int SET, int A, typename S, typename R>
-__device__ __forceinline__ R pull(const Ctx<R>& c, const S* __restrict__ src, int x, int y)
+// Post-streaming population X_a at node m (unwrapped tile coordinates u, in
+// the lattice after periodic wrapping m), relative to w_a * base, where base
+// is the node's own storage reference of the set: X_a(m) = X~_a(m - e_a)
+// (pull).  A source beyond a wall gives halfway bounce-back
+// X_a(m) = X~_abar(m), or for a Dirichlet scalar (h: T_w(m - e_a/2); q:
+// psi_w) the anti-bounce-back X_a(m) = -X~_abar(m) + 2 w_a X_w.  A source
+// beyond both a y-wall and an x-wall follows the y-wall's rule.  INT: the
+// caller guarantees every source lies inside the lattice (no wrap, no wall).
+// RF(ux, uy) returns the per-node reference of set SET at unwrapped node u.
+template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
+__device__ __forceinline__ R pull(const Ctx<R>& c, const S* __restrict__ src, int ux, int uy, int mx, int my, R base,
+                                  const RF& rf)
 {
     constexpr int EX = ex(A), EY = ey(A);
-    int sx = x - EX, sy = y - EY;
-    if (EX != 0 && !c.wallx) sx = sx < 0 ? sx + c.nx : (sx >= c.nx ? sx - c.nx : sx);
-    if (EY != 0 && !c.wally) sy = sy < 0 ? sy + c.ny : (sy >= c.ny ? sy - c.ny : sy);
-    const bool outy = (EY != 0) && (sy < 0 || sy >= c.ny);
-    const bool outx = (EX != 0) && (sx < 0 || sx >= c.nx);
-    if (!outx && !outy) {
-        const R v = dec<S, R>(src[(int64_t)(SET * 9 + A) * c.plane + (int64_t)sy * c.pitch + sx], c.inv_scale);
-        if (SET == SET_H && EX != 0) {
-            // re-reference from column sx to column x (h deviations only)
-            if (c.refs) return v + R(wt(A)) * c.gradT * R(sx - x);
+    constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q);
+    const R w = R(wt(A));
+    int sx = mx - EX, sy = my - EY;
+    bool wall = false;
+    int side = 0;
+    if (!INT) {
+        if (EY != 0 && (sy < 0 || sy >= c.ny)) {
+            if (c.wally) { wall = true; side = sy < 0 ? 2 : 3; }
+            else sy += sy < 0 ? c.ny : -c.ny;
         }
+        if (EX != 0 && !wall && (sx < 0 || sx >= c.nx)) {
+            if (c.wallx) { wall = true; side = sx < 0 ? 0 : 1; }
+            else sx += sx < 0 ? c.nx : -c.nx;
+        }
+    }
+    if (!wall) {
+        R v = dec<S, R>(src[(int64_t)(SET * 9 + A) * c.plane + (int64_t)sy * c.pitch + sx], c.inv_scale);
+        if (NODE_REF) v += w * (rf(ux - EX, uy - EY) - base);
+        if (REFS && SET == SET_H && EX != 0) v += w * c.gradT * R(sx - mx);  // linear-law reference of column sx
         return v;
     }
     constexpr int B = opp(A);
-    const R v = dec<S, R>(src[(int64_t)(SET * 9 + B) * c.plane + (int64_t)y * c.pitch + x], c.inv_scale);
-    if (SET != SET_H && SET != SET_Q) return v;
-    const int side = outy ? (sy < 0 ? 2 : 3) : (sx < 0 ? 0 : 1);
-    if (SET == SET_H) {
-        if (!c.t_dir(side)) return v;
-        // 2 w_a (T_w(x - e_a/2) - Tref(x)); with the linear-law reference the
-        // difference is exactly -gradT * ex / 2.
-        const R d = c.refs ? R(-0.5) * c.gradT * R(EX) : c.Tlaw(R(x) - R(0.5) * R(EX));
-        return -v + R(2.0 * wt(A)) * d;
+    R v = dec<S, R>(src[(int64_t)(SET * 9 + B) * c.plane + (int64_t)my * c.pitch + mx], c.inv_scale);
+    if (NODE_REF) v += w * (rf(ux, uy) - base);
+    if (SET == SET_H && c.t_dir(side)) {
+        // X_w - base; with the linear-law reference exactly -gradT ex / 2
+        const R d = REFS ? R(-0.5) * c.gradT * R(EX) : c.Tlaw(R(mx) - R(0.5) * R(EX)) - base;
+        return -v + R(2) * w * d;
     }
-    if (!c.p_dir(side)) return v;
-    return -v + R(2.0 * wt(A)) * (c.psi_wall(side) - c.qref());
+    if (SET == SET_Q && c.p_dir(side)) return -v + R(2) * w * (c.psi_wall(side) - base);
+    return v;
 }
 
-template <int SET, typename S, typename R>
-__device__ __forceinline__ void pull9(const Ctx<R>& c, const S* __restrict__ src, int x, int y, R v[9])
+template <int SET, bool INT, bool REFS, typename S, typename R, typename RF>
+__device__ __forceinline__ void pull9(const Ctx<R>& c, const S* __restrict__ src, int ux, int uy, int mx, int my,
+                                      R base, const RF& rf, R v[9])
 {
-    v[0] = pull<SET, 0, S, R>(c, src, x, y);
-    v[1] = pull<SET, 1, S, R>(c, src, x, y);
-    v[2] = pull<SET, 2, S, R>(c, src, x, y);
-    v[3] = pull<SET, 3, S, R>(c, src, x, y);
-    v[4] = pull<SET, 4, S, R>(c, src, x, y);
-    v[5] = pull<SET, 5, S, R>(c, src, x, y);
-    v[6] = pull<SET, 6, S, R>(c, src, x, y);
-    v[7] = pull<SET, 7, S, R>(c, src, x, y);
-    v[8] = pull<SET, 8, S, R>(c, src, x, y);
+    v[0] = pull<SET, 0, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[1] = pull<SET, 1, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[2] = pull<SET, 2, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[3] = pull<SET, 3, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[4] = pull<SET, 4, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[5] = pull<SET, 5, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[6] = pull<SET, 6, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[7] = pull<SET, 7, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    v[8] = pull<SET, 8, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
 }
 
 template <typename R>
@@ -171,62 +195,30 @@ __device__ __forceinline__ R sum9(const R v[9])
     return s;
 }
 
-// --------------------------------------------------------- ghost nodes
-// A node outside the lattice takes the value of its mirror node across the
-// wall (zero normal gradient), or 2 X_w - X(mirror) on a Dirichlet wall;
-// periodic axes wrap.  The y rule is applied at the mirrored column, then
-// the x rule.
-struct GhostMap {
-    int ix, iy, xside, yside;
-};
-
-template <typename R>
-__device__ __forceinline__ GhostMap ghost_map(const Ctx<R>& c, int gx, int gy)
-{
-    GhostMap m;
-    gx = gx < -2 ? -2 : (gx > c.nx + 1 ? c.nx + 1 : gx);
-    gy = gy < -2 ? -2 : (gy > c.ny + 1 ? c.ny + 1 : gy);
-    if (!c.wallx) gx = gx < 0 ? gx + c.nx : (gx >= c.nx ? gx - c.nx : gx);
-    if (!c.wally) gy = gy < 0 ? gy + c.ny : (gy >= c.ny ? gy - c.ny : gy);
-    m.xside = -1;
-    m.yside = -1;
-    if (gx < 0) { m.xside = 0; gx = -1 - gx; }
-    else if (gx >= c.nx) { m.xside = 1; gx = 2 * c.nx - 1 - gx; }
-    if (gy < 0) { m.yside = 2; gy = -1 - gy; }
-    else if (gy >= c.ny) { m.yside = 3; gy = 2 * c.ny - 1 - gy; }
-    m.ix = gx;
-    m.iy = gy;
-    return m;
-}
-
-template <typename R>
-__device__ __forceinline__ R ghost_T(const Ctx<R>& c, const GhostMap& m, R T)
-{
-    if (m.yside >= 0 && c.t_dir(m.yside)) T = R(2) * c.Tlaw(R(m.ix)) - T;
-    if (m.xside >= 0 && c.t_dir(m.xside)) T = R(2) * c.Tlaw(m.xside ? R(c.nx) - R(0.5) : R(-0.5)) - T;
-    return T;
-}
-
-template <typename R>
-__device__ __forceinline__ R ghost_psi(const Ctx<R>& c, const GhostMap& m, R p)
-{
-    if (m.yside >= 0 && c.p_dir(m.yside)) p = R(2) * c.psi_wall(m.yside) - p;
-    if (m.xside >= 0 && c.p_dir(m.xside)) p = R(2) * c.psi_wall(m.xside) - p;
-    return p;
-}
-
 // ------------------------------------------------------ material laws
 // Surface tension (Sec. 2.1): law 1 as printed, law 0 the multiplicative
-// Langmuir variant; the log argument is floored at 1e-6.
+// Langmuir variant; the log argument is floored at 1e-6.  Evaluated in FP64:
+// along the channel sigma changes by ~1e-3 of itself per node, so its
+// gradient is a difference that FP32 would resolve only to ~1e-4.
 template <typename R>
-__device__ __forceinline__ R sigma_of(const Ctx<R>& c, R T, R psi)
+__device__ __forceinline__ double sigma_of(const Ctx<R>& c, double T, double psi)
 {
-    const R dT = T - c.Tref;
-    R frac = psi * c.inv_psi_inf;
-    frac = frac > R(1.0 - 1e-6) ? R(1.0 - 1e-6) : frac;
-    const R L = log(R(1) - frac);
-    if (c.law == 1) return c.s0 + c.s0 * c.beta * (T / c.Tref) * L + c.sT * dT + c.sTT * dT * dT;
-    return (c.s0 + c.sT * dT + c.sTT * dT * dT) * (R(1) + c.beta * L);
+    const double dT = T - c.Trefd;
+    double frac = psi * c.ipsid;
+    frac = frac > 1.0 - 1e-6 ? 1.0 - 1e-6 : frac;
+    const double L = log(1.0 - frac);
+    if (c.law == 1) return c.s0d + c.s0d * c.betad * (T / c.Trefd) * L + c.sTd * dT + c.sTTd * dT * dT;
+    return (c.s0d + c.sTd * dT + c.sTTd * dT * dT) * (1.0 + c.betad * L);
+}
+
+// Derivative of the surfactant potential over lambda (Sec. 2):
+// V/lambda = -(s/lambda)(8/W^2) phi^2 (1-phi)^2 + (w/lambda)/2 (phi - 1/2)^2.
+// omphi = 1 - phi, passed separately (it is formed without cancellation).
+template <typename R>
+__device__ __forceinline__ R dV_lam(const Ctx<R>& c, R phi, R omphi)
+{
+    const R a = R(8) / (c.W * c.W);
+    return -c.s_lam * a * R(2) * phi * omphi * (omphi - phi) + c.w_lam * (phi - R(0.5));
 }
 
 // ----------------------------------------------------------- collisions
@@ -250,17 +242,19 @@ __device__ __forceinline__ void raw_to_pop(const R m[9], R o[9])
 // Advection-diffusion central-moment collision (f: App. B, h: App. D,
 // q: App. E).  Post-collision central moments are
 // (X, a_x, a_y, X/3, X/3, 0, 0, 0, X/9) with a = k1 + w1 (j_eq - k1), k1 the
-// pre-collision first central moment.  Populations enter and leave as
-// deviations d_a = X_a - w_a Xr from a reference Xr; with X = Xr + sum d:
-//   d~ = w Xdev + P^-1 [ X dM(u) + A(u, a) ],
+// pre-collision first central moment.  Populations enter as deviations
+// d_a = X_a - w_a Xin and leave as deviations from w_a Xout; with
+// X = Xin + sum d:
+//   d~ = w (X - Xout) + P^-1 [ X dM(u) + A(u, a) ],
 // dM(u) = F^-1(u)(1,0,0,1/3,1/3,0,0,0,1/9) minus its u = 0 value and
-// A(u, a) = F^-1(u)(0, a_x, a_y, 0, ...).  With Xr = 0 this is the plain
-// P^-1 F^-1(u) of the post-collision central moments.
+// A(u, a) = F^-1(u)(0, a_x, a_y, 0, ...).  With Xin = Xout = 0 this is the
+// plain P^-1 F^-1(u) of the post-collision central moments.
 template <typename R>
-__device__ __forceinline__ void collide_ad(R d[9], R Xr, R jx, R jy, R w1, R ux, R uy)
+__device__ __forceinline__ void collide_ad(R d[9], R Xin, R Xout, R jx, R jy, R w1, R ux, R uy)
 {
     const R Xd = sum9(d);
-    const R X = Xr + Xd;
+    const R X = Xin + Xd;
+    const R Xshift = (Xin - Xout) + Xd;  // X - Xout without forming X first
     const R mx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
     const R my = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
     const R kx = mx - ux * X, ky = my - uy * X;
@@ -280,7 +274,7 @@ __device__ __forceinline__ void collide_ad(R d[9], R Xr, R jx, R jy, R w1, R ux,
     R o[9];
     raw_to_pop(v, o);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) d[a] = R(wt(a)) * Xd + o[a];
+    for (int a = 0; a < 9; ++a) d[a] = R(wt(a)) * Xshift + o[a];
 }
 
 // Two-fluid central-moment collision (App. C): every moment relaxes with
@@ -337,15 +331,6 @@ __device__ __forceinline__ void collide_g(R g[9], R pstar, R jx, R jy, R p, R rh
     raw_to_pop(m, g);
 }
 
-// Derivative of the surfactant potential over lambda (Sec. 2):
-// V/lambda = -(s/lambda)(8/W^2) phi^2 (1-phi)^2 + (w/lambda)/2 (phi - 1/2)^2.
-template <typename R>
-__device__ __forceinline__ R dV_lam(const Ctx<R>& c, R phi)
-{
-    const R a = R(8) / (c.W * c.W);
-    return -c.s_lam * a * R(2) * phi * (R(1) - phi) * (R(1) - R(2) * phi) + c.w_lam * (phi - R(0.5));
-}
-
 // ------------------------------------------------------------ tile body
 enum { MODE_STEP = 0, MODE_MACRO = 1 };
 
@@ -357,59 +342,168 @@ struct MacroOut {
 };
 enum { NDIAG_PART = 16 };
 
-template <typename R, int BX, int BY>
+// LDS of one tile.  E3 = tile + 3 halo (storage references), E2 = tile + 2
+// (phi), E1 = tile + 1 (sigma, p*, T, psi, normal).  phi is held as a
+// base (per-node reference, exact) plus a deviation.
+template <typename R, int BX, int BY, bool REFS>
 struct Smem {
-    static constexpr int W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
-    R phi[H2 * W2];
-    R ps[H1 * W1];
-    R sig[H1 * W1];
-    R nx[H1 * W1];
-    R ny[H1 * W1];
+    static constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
+    static constexpr int N3 = REFS ? W3 * H3 : 1;
+    static constexpr int N2B = REFS ? W2 * H2 : 1;
+    R rf[N3];   // phi reference
+    R rq[N3];   // psi reference
+    R phd[W2 * H2];
+    R phb[N2B];
+    double sg[W1 * H1];  // sigma (FP64)
+    R ps[W1 * H1];
+    R ts[W1 * H1];   // T - T_w(x): deviation from the linear wall law at the slot's column
+    R pq[W1 * H1];   // psi
+    R nx[W1 * H1];
+    R ny[W1 * H1];
 };
 
-template <typename R, typename S, int BX, int BY, int MODE>
-__device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const S* __restrict__ src, S* __restrict__ dst,
-                          Smem<R, BX, BY>& sh, const MacroOut& mo, double* dacc)
+// Isotropic gradient (the paper's isotropic finite differences, Sec. 3):
+// [4(E - W) + (NE - NW) + (SE - SW)] / 12 and its y analogue, applied to a
+// field held as base + deviation (differences taken per part).
+template <typename R, bool REFS, typename T = R>
+__device__ __forceinline__ void grad2(const T* D, const T* B, int p, int W, T& gx, T& gy)
 {
+    const int e = p + 1, w = p - 1, n = p + W, s = p - W;
+    T dx = T(4) * (D[e] - D[w]) + (D[n + 1] - D[n - 1]) + (D[s + 1] - D[s - 1]);
+    T dy = T(4) * (D[n] - D[s]) + (D[n + 1] - D[s + 1]) + (D[n - 1] - D[s - 1]);
+    if (REFS) {
+        dx += T(4) * (B[e] - B[w]) + (B[n + 1] - B[n - 1]) + (B[s + 1] - B[s - 1]);
+        dy += T(4) * (B[n] - B[s]) + (B[n + 1] - B[s + 1]) + (B[n - 1] - B[s - 1]);
+    }
+    gx = dx * T(1.0 / 12.0);
+    gy = dy * T(1.0 / 12.0);
+}
+
+template <typename R, typename S, int BX, int BY, int MODE, bool INT>
+__device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const S* __restrict__ src, S* __restrict__ dst,
+                                          const __half* __restrict__ rsrc, __half* __restrict__ rdst,
+                                          Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc)
+{
+    constexpr bool REFS = sizeof(R) == 4;
     constexpr int NT = 256;
-    constexpr int W2 = BX + 4, H2 = BY + 4, W1 = BX + 2;
+    constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     const int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
+    const int64_t rplane = c.plane;  // reference planes share the population pitch
 
-    // ---- phase 1: phi on tile + 2 halo; p*, sigma on tile + 1 halo
+    // per-node references of the f and q sets at unwrapped tile coordinates
+    auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
+    auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
+    auto no_ref = [&](int, int) -> R { return R(0); };
+    // lattice node of an unwrapped coordinate on a periodic axis
+    auto wrapx = [&](int u) { return INT || c.wallx ? u : (u < 0 ? u + c.nx : (u >= c.nx ? u - c.nx : u)); };
+    auto wrapy = [&](int u) { return INT || c.wally ? u : (u < 0 ? u + c.ny : (u >= c.ny ? u - c.ny : u)); };
+    // node beyond a wall (ghost)
+    auto ghostx = [&](int u) { return !INT && c.wallx && (u < 0 || u >= c.nx); };
+    auto ghosty = [&](int u) { return !INT && c.wally && (u < 0 || u >= c.ny); };
+
+    // ---- phase 0: storage references on tile + 3 halo
+    if (REFS) {
+        for (int k = tid; k < W3 * H3; k += NT) {
+            const int ux = x0 - 3 + k % W3, uy = y0 - 3 + k / W3;
+            R a = R(0), b = R(0);
+            if (!ghostx(ux) && !ghosty(uy)) {
+                int mx = wrapx(ux), my = wrapy(uy);
+                // beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
+                if (mx >= 0 && mx < c.nx && my >= 0 && my < c.ny) {
+                    const int64_t o = (int64_t)my * c.pitch + mx;
+                    a = R(__half2float(rsrc[o]));
+                    b = R(__half2float(rsrc[rplane + o]));
+                }
+            }
+            sh.rf[k] = a;
+            sh.rq[k] = b;
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 1a: phi on tile + 2 halo; p*, T, psi on tile + 1 halo (lattice nodes)
     for (int k = tid; k < W2 * H2; k += NT) {
         const int lx = k % W2, ly = k / W2;
-        const GhostMap m = ghost_map(c, x0 - 2 + lx, y0 - 2 + ly);
+        const int ux = x0 - 2 + lx, uy = y0 - 2 + ly;
+        const bool in1 = lx >= 1 && lx <= BX + 2 && ly >= 1 && ly <= BY + 2;
+        const int e1 = (ly - 1) * W1 + (lx - 1);
+        const int mx = wrapx(ux), my = wrapy(uy);
+        // ghosts are filled in phase 1b; beyond one wrap no live node reads the slot
+        if (ghostx(ux) || ghosty(uy) || (!INT && (mx < 0 || mx >= c.nx || my < 0 || my >= c.ny))) continue;
         R v[9];
-        pull9<SET_F>(c, src, m.ix, m.iy, v);
-        sh.phi[k] = sum9(v);
-        if (lx >= 1 && lx <= BX + 2 && ly >= 1 && ly <= BY + 2) {
-            const int e = (ly - 1) * W1 + (lx - 1);
-            pull9<SET_G>(c, src, m.ix, m.iy, v);
-            sh.ps[e] = sum9(v);  // zero normal gradient at walls: mirror value as is
-            pull9<SET_H>(c, src, m.ix, m.iy, v);
-            const R T = ghost_T(c, m, c.Tref_x(m.ix) + sum9(v));
-            pull9<SET_Q>(c, src, m.ix, m.iy, v);
-            const R psi = ghost_psi(c, m, c.qref() + sum9(v));
-            sh.sig[e] = sigma_of(c, T, psi);
+        const R bf = ref_f(ux, uy);
+        pull9<SET_F, INT, REFS>(c, src, ux, uy, mx, my, bf, ref_f, v);
+        sh.phd[k] = sum9(v);
+        if (REFS) sh.phb[k] = bf;
+        if (in1) {
+            pull9<SET_G, INT, REFS>(c, src, ux, uy, mx, my, R(0), no_ref, v);
+            sh.ps[e1] = sum9(v);
+            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+            pull9<SET_H, INT, REFS>(c, src, ux, uy, mx, my, bh, no_ref, v);
+            // T - T_w(ux): with the linear-law reference exactly gradT (mx - ux) + sum
+            sh.ts[e1] = REFS ? c.gradT * R(mx - ux) + sum9(v) : R((double)sum9(v) - c.Tlaw_d((double)ux));
+            const R bq = ref_q(ux, uy);
+            pull9<SET_Q, INT, REFS>(c, src, ux, uy, mx, my, bq, ref_q, v);
+            sh.pq[e1] = bq + sum9(v);
         }
     }
     __syncthreads();
 
-    // ---- phase 2: unit normal n = grad phi / |grad phi| on tile + 1 halo
-    for (int e = tid; e < W1 * (BY + 2); e += NT) {
-        const int lx = e % W1 + 1, ly = e / W1 + 1;  // in phi (E2) coordinates
-        const R* P = sh.phi;
-        const R gx = (R(4) * (P[ly * W2 + lx + 1] - P[ly * W2 + lx - 1]) + P[(ly + 1) * W2 + lx + 1] -
-                      P[(ly + 1) * W2 + lx - 1] + P[(ly - 1) * W2 + lx + 1] - P[(ly - 1) * W2 + lx - 1]) *
-                     R(1.0 / 12.0);
-        const R gy = (R(4) * (P[(ly + 1) * W2 + lx] - P[(ly - 1) * W2 + lx]) + P[(ly + 1) * W2 + lx + 1] -
-                      P[(ly - 1) * W2 + lx + 1] + P[(ly + 1) * W2 + lx - 1] - P[(ly - 1) * W2 + lx - 1]) *
-                     R(1.0 / 12.0);
+    // ---- phase 1b: ghost nodes beyond walls take their mirror node's value
+    // (zero normal gradient) or 2 X_w - X(mirror) for Dirichlet T / psi; the
+    // y rule is applied at the mirrored column, then the x rule.
+    if (!INT) {
+        for (int k = tid; k < W2 * H2; k += NT) {
+            const int lx = k % W2, ly = k / W2;
+            const int ux = x0 - 2 + lx, uy = y0 - 2 + ly;
+            const bool gx = ghostx(ux), gy = ghosty(uy);
+            if (!gx && !gy) continue;
+            int xs = -1, ys = -1, mx = wrapx(ux), my = wrapy(uy);
+            if (gx) { xs = ux < 0 ? 0 : 1; mx = ux < 0 ? -1 - ux : 2 * c.nx - 1 - ux; }
+            if (gy) { ys = uy < 0 ? 2 : 3; my = uy < 0 ? -1 - uy : 2 * c.ny - 1 - uy; }
+            // the mirror slot in unwrapped coordinates: along a wall axis the
+            // mirrored lattice coordinate, along a periodic axis the slot's own
+            const int mux = gx ? mx : ux, muy = gy ? my : uy;
+            const int mlx = mux - (x0 - 2), mly = muy - (y0 - 2);
+            // mirrors outside the window belong to halo nodes no live node reads
+            if (mlx < 0 || mlx >= W2 || mly < 0 || mly >= H2 || ux < -2 || ux > c.nx + 1 || uy < -2 ||
+                uy > c.ny + 1) {
+                sh.phd[k] = R(0);
+                if (REFS) sh.phb[k] = R(0);
+                continue;
+            }
+            const int km = mly * W2 + mlx;
+            sh.phd[k] = sh.phd[km];
+            if (REFS) sh.phb[k] = sh.phb[km];
+            const bool in1 = lx >= 1 && lx <= BX + 2 && ly >= 1 && ly <= BY + 2;
+            if (in1 && mlx >= 1 && mlx <= BX + 2 && mly >= 1 && mly <= BY + 2) {
+                const int e1 = (ly - 1) * W1 + (lx - 1), m1 = (mly - 1) * W1 + (mlx - 1);
+                sh.ps[e1] = sh.ps[m1];
+                double T = c.Tlaw_d((double)mux) + (double)sh.ts[m1];
+                R q = sh.pq[m1];
+                if (ys >= 0 && c.t_dir(ys)) T = 2.0 * c.Tlaw_d((double)mx) - T;
+                if (xs >= 0 && c.t_dir(xs)) T = 2.0 * c.Tlaw_d(xs ? c.nx - 0.5 : -0.5) - T;
+                if (ys >= 0 && c.p_dir(ys)) q = R(2) * c.psi_wall(ys) - q;
+                if (xs >= 0 && c.p_dir(xs)) q = R(2) * c.psi_wall(xs) - q;
+                sh.ts[e1] = R(T - c.Tlaw_d((double)ux));
+                sh.pq[e1] = q;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 2: unit normal n = grad phi / |grad phi| and sigma(T, psi) on tile + 1 halo
+    for (int e = tid; e < W1 * H1; e += NT) {
+        const int lx = e % W1 + 1, ly = e / W1 + 1;  // E2 coordinates
+        R gx, gy;
+        grad2<R, REFS>(sh.phd, sh.phb, ly * W2 + lx, W2, gx, gy);
         R mag = sqrt(gx * gx + gy * gy);
         mag = mag < R(1e-12) ? R(1e-12) : mag;
         sh.nx[e] = gx / mag;
         sh.ny[e] = gy / mag;
+        const int ux = x0 - 1 + e % W1;
+        sh.sg[e] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
     }
     __syncthreads();
 
@@ -418,16 +512,16 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
     const int lx = tid % BX;
     for (int ly = tid / BX; ly < BY; ly += ROWS) {
         const int x = x0 + lx, y = y0 + ly;
-        const bool live = (x < c.nx) && (y < c.ny);
-        // stencil helpers (E2 coords: +2, E1 coords: +1)
+        const bool live = INT || ((x < c.nx) && (y < c.ny));
         const int p2 = (ly + 2) * W2 + (lx + 2);
         const int p1 = (ly + 1) * W1 + (lx + 1);
-        const R* P = sh.phi;
-        const R phi = P[p2];
-        const R gx = (R(4) * (P[p2 + 1] - P[p2 - 1]) + P[p2 + W2 + 1] - P[p2 + W2 - 1] + P[p2 - W2 + 1] -
-                      P[p2 - W2 - 1]) * R(1.0 / 12.0);
-        const R gy = (R(4) * (P[p2 + W2] - P[p2 - W2]) + P[p2 + W2 + 1] - P[p2 - W2 + 1] + P[p2 + W2 - 1] -
-                      P[p2 - W2 - 1]) * R(1.0 / 12.0);
+        R gx, gy;
+        grad2<R, REFS>(sh.phd, sh.phb, p2, W2, gx, gy);
+        const R phb = REFS ? sh.phb[p2] : R(0);
+        const R phi = phb + sh.phd[p2];
+        // 1 - phi from the reference / deviation pair: inside a bubble phi is ~1
+        // and 1 - phi formed from phi itself would keep only ~3 digits in FP32
+        const R omphi = (R(1) - phb) - sh.phd[p2];
         const R nxv = sh.nx[p1], nyv = sh.ny[p1];
         // curvature: isotropic divergence of the normal field
         const R* NX = sh.nx;
@@ -436,18 +530,13 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
                        (NX[p1 + W1 + 1] - NX[p1 + W1 - 1] + NX[p1 - W1 + 1] - NX[p1 - W1 - 1]) +
                        (NY[p1 + W1 + 1] - NY[p1 - W1 + 1] + NY[p1 + W1 - 1] - NY[p1 - W1 - 1])) *
                       R(1.0 / 12.0);
-        const R* SG = sh.sig;
-        const R sig = SG[p1];
-        const R dsx = (R(4) * (SG[p1 + 1] - SG[p1 - 1]) + SG[p1 + W1 + 1] - SG[p1 + W1 - 1] + SG[p1 - W1 + 1] -
-                       SG[p1 - W1 - 1]) * R(1.0 / 12.0);
-        const R dsy = (R(4) * (SG[p1 + W1] - SG[p1 - W1]) + SG[p1 + W1 + 1] - SG[p1 - W1 + 1] + SG[p1 + W1 - 1] -
-                       SG[p1 - W1 - 1]) * R(1.0 / 12.0);
-        const R* PS = sh.ps;
-        const R pstar = PS[p1];
-        const R dpx = (R(4) * (PS[p1 + 1] - PS[p1 - 1]) + PS[p1 + W1 + 1] - PS[p1 + W1 - 1] + PS[p1 - W1 + 1] -
-                       PS[p1 - W1 - 1]) * R(1.0 / 12.0);
-        const R dpy = (R(4) * (PS[p1 + W1] - PS[p1 - W1]) + PS[p1 + W1 + 1] - PS[p1 - W1 + 1] + PS[p1 + W1 - 1] -
-                       PS[p1 - W1 - 1]) * R(1.0 / 12.0);
+        double dsxd, dsyd;
+        grad2<R, false, double>(sh.sg, nullptr, p1, W1, dsxd, dsyd);
+        const R dsx = R(dsxd), dsy = R(dsyd);
+        R dpx, dpy;
+        grad2<R, false, R>(sh.ps, nullptr, p1, W1, dpx, dpy);
+        const R sig = R(sh.sg[p1]);
+        const R pstar = sh.ps[p1];
 
         // CSF surface force: 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
         const R ds = R(1.5) * c.W * (gx * gx + gy * gy);
@@ -470,21 +559,23 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
 
         // g: momentum, velocity and pressure
         R g[9];
-        pull9<SET_G>(c, src, x, y, g);
+        pull9<SET_G, INT, REFS>(c, src, x, y, x, y, R(0), no_ref, g);
         const R jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
         const R jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
         const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
         const R uy = (jy + R(0.5) * cs2 * Fty) / (rho * cs2);
         const R p = pstar + R(0.5) * (Fpx * ux + Fpy * uy);
-        const R dV = dV_lam(c, phi);
+        const R dV = dV_lam(c, phi, omphi);
+        const R bh = REFS ? c.Tlaw(R(x)) : R(0);
+        const R bq = ref_q(x, y);
 
         if (MODE == MODE_MACRO) {
             R hv[9], qv[9], fv[9];
-            pull9<SET_H>(c, src, x, y, hv);
-            pull9<SET_Q>(c, src, x, y, qv);
-            pull9<SET_F>(c, src, x, y, fv);
-            const R T = c.Tref_x(x) + sum9(hv);
-            const R psi = c.qref() + sum9(qv);
+            pull9<SET_H, INT, REFS>(c, src, x, y, x, y, bh, no_ref, hv);
+            pull9<SET_Q, INT, REFS>(c, src, x, y, x, y, bq, ref_q, qv);
+            pull9<SET_F, INT, REFS>(c, src, x, y, x, y, phb, ref_f, fv);
+            const R T = bh + sum9(hv);
+            const R psi = bq + sum9(qv);
             if (mo.fields) {
                 const int64_t n = (int64_t)c.nx * c.ny, k = (int64_t)y * c.nx + x;
                 const R vals[18] = {phi, p, ux, uy, T, psi, gx, gy, kap, sig, Fsx, Fsy, Fpx, Fpy,
@@ -523,29 +614,36 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
 #pragma unroll
         for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_G * 9 + a) * c.plane + o] = enc<S, R>(g[a], c.scale);
 
-        // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W
+        // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
+        // the new storage reference is the FP16-rounded phi of this node
         R f[9];
-        pull9<SET_F>(c, src, x, y, f);
-        const R mt = c.Mphi * R(4) * phi * (R(1) - phi) / c.W;
-        collide_ad(f, R(0), mt * nxv, mt * nyv, c.om_phi, ux, uy);
+        pull9<SET_F, INT, REFS>(c, src, x, y, x, y, phb, ref_f, f);
+        const R mt = c.Mphi * R(4) * phi * omphi / c.W;
+        const R nbf = REFS ? R(__half2float(__float2half_rn((float)phi))) : R(0);
+        collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
 #pragma unroll
         for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_F * 9 + a) * c.plane + o] = enc<S, R>(f[a], c.scale);
 
         // h: temperature
         R hh[9];
-        pull9<SET_H>(c, src, x, y, hh);
-        collide_ad(hh, c.Tref_x(x), R(0), R(0), omT, ux, uy);
+        pull9<SET_H, INT, REFS>(c, src, x, y, x, y, bh, no_ref, hh);
+        collide_ad(hh, bh, bh, R(0), R(0), omT, ux, uy);
 #pragma unroll
         for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_H * 9 + a) * c.plane + o] = enc<S, R>(hh[a], c.scale);
 
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
         R qq[9];
-        pull9<SET_Q>(c, src, x, y, qq);
-        const R psi = c.qref() + sum9(qq);
+        pull9<SET_Q, INT, REFS>(c, src, x, y, x, y, bq, ref_q, qq);
+        const R psi = bq + sum9(qq);
         const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
-        collide_ad(qq, c.qref(), mf * gx, mf * gy, c.om_psi, ux, uy);
+        const R nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
+        collide_ad(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
 #pragma unroll
         for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_Q * 9 + a) * c.plane + o] = enc<S, R>(qq[a], c.scale);
+        if (REFS) {
+            rdst[o] = __float2half_rn((float)nbf);
+            rdst[rplane + o] = __float2half_rn((float)nbq);
+        }
     }
 }
 

@@ -32,16 +32,19 @@ def maxrel(a, b):
     return float(np.max(np.abs(a - b)) / scale) if scale > 0 else float(np.max(np.abs(a - b)))
 
 
-def compare(gf, of, names=("phi", "p", "u", "T", "psi")):
+def compare(gf, of, names=("phi", "p", "u", "T", "psi"), floor=None):
     """max-rel per field; the velocity u = (ux, uy) is one (vector) field,
-    measured against max |u|."""
+    measured against max |u|.  `floor` gives a field a scale of the problem
+    to measure against where the field itself is (physically) zero."""
+    floor = floor or {}
     out = {}
     for k in names:
         if k == "u":
-            scale = np.max(np.hypot(of["ux"], of["uy"]))
+            scale = max(np.max(np.hypot(of["ux"], of["uy"])), floor.get(k, 0.0))
             out[k] = float(np.max(np.hypot(gf["ux"] - of["ux"], gf["uy"] - of["uy"])) / scale)
         else:
-            out[k] = maxrel(gf[k], of[k])
+            scale = max(np.max(np.abs(of[k])), floor.get(k, 0.0))
+            out[k] = float(np.max(np.abs(gf[k] - of[k])) / scale)
     return out
 
 
@@ -116,7 +119,11 @@ def test_fp64_boundary_variants(env, variant):
         # noise keeps the interface normal defined where grad phi vanishes by symmetry
         p = dict(cases.flat_surfactant(0.15, ny=40, nx=5), phi_noise=1e-6)
     s, o = run_pair(env, p, 40)
-    err = compare(s.fields(), o.fields())
+    # a flat interface carries no Laplace pressure and drives no flow: there p
+    # and u are rounding noise, measured against the capillary scales
+    # sigma0/W and sigma0/mu_A of the case
+    floor = {"p": p["sigma0"] / p["W"], "u": p["sigma0"] / (p["rho_A"] * p["nu_A"])} if variant == "tiny" else None
+    err = compare(s.fields(), o.fields(), floor=floor)
     assert max(err.values()) <= 1e-12, err
 
 

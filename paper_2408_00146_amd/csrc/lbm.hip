@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "lbm.h"
@@ -43,20 +44,26 @@ template <typename R, typename S, int BX, int BY, int MODE>
 __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int x0, int y0, int b, Smem<R, BX, BY, sizeof(R) == 4>& sh,
                                          const MacroOut& mo, double* dacc)
 {
-    const S* src = (const S*)cd.buf[b];
-    S* dst = MODE == MODE_STEP ? (S*)cd.buf[b ^ 1] : nullptr;
-    const __half* rsrc = cd.rbuf[b];
-    __half* rdst = MODE == MODE_STEP ? cd.rbuf[b ^ 1] : nullptr;
+    const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
+    const View dst{make_rsrc(cd.buf[b ^ 1], MODE == MODE_STEP ? cd.pop_bytes : 0u)};
+    const Rsrc rsrc = make_rsrc(cd.rbuf[b], cd.ref_bytes);
+    const Rsrc rdst = make_rsrc(cd.rbuf[b ^ 1], MODE == MODE_STEP ? cd.ref_bytes : 0u);
     if (interior(cd, x0, y0, BX, BY))
         tile_body<R, S, BX, BY, MODE, true>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
     else
         tile_body<R, S, BX, BY, MODE, false>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
 }
 
-template <typename R, int BX, int BY>
+// Storage selection of a step launch: one storage type per kernel keeps the
+// code of a single tile body in the instruction cache; handles that mix
+// FP32 and FP16 cases use the kernel that branches per tile.
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
+
+template <int ST, int BX, int BY>
 __global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
                                               int ntiles, const int64_t* __restrict__ steps, int t)
 {
+    using R = typename std::conditional<ST == ST_F64, double, float>::type;
     __shared__ Smem<R, BX, BY, sizeof(R) == 4> sh;
     const TileRec tr = tiles[xcd_remap(blockIdx.x, ntiles)];
     const CaseDev& cd = cases[tr.c];
@@ -66,8 +73,12 @@ __global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases,
     c.load(cd);
     const MacroOut mo{nullptr, 0u, nullptr};
     const int b = (int)(s & 1);
-    if constexpr (sizeof(R) == 8) {
+    if constexpr (ST == ST_F64) {
         run_tile<double, double, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+    } else if constexpr (ST == ST_F32) {
+        run_tile<float, float, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+    } else if constexpr (ST == ST_F16) {
+        run_tile<float, __half, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
     } else {
         if (cd.prec == PREC_FP16S) run_tile<float, __half, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
         else run_tile<float, float, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
@@ -284,12 +295,12 @@ __global__ void k_store(const CaseDev* __restrict__ cases, int case_id, StateSrc
 // [4][9][ny][nx] (full values): the same pull the step performs, with the
 // per-node references read from global memory.
 template <int SET, typename S, typename R, typename RF>
-__device__ __forceinline__ void export_set(const Ctx<R>& c, const S* src, int x, int y, double* out, int64_t n, R base,
+__device__ __forceinline__ void export_set(const Ctx<R>& c, View src, int x, int y, double* out, int64_t n, R base,
                                            const RF& rf)
 {
     constexpr bool REFS = sizeof(R) == 4;
     R v[9];
-    pull9<SET, false, REFS>(c, src, x, y, x, y, base, rf, v);
+    pull9<SET, false, REFS, S>(c, src, x, y, x, y, base, rf, v);
     const int64_t k = (int64_t)y * c.nx + x;
 #pragma unroll
     for (int a = 0; a < 9; ++a) out[(int64_t)(SET * 9 + a) * n + k] = (double)v[a] + wt(a) * (double)base;
@@ -301,7 +312,7 @@ __device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
     constexpr bool REFS = sizeof(R) == 4;
     Ctx<R> c;
     c.load(cd);
-    const S* src = (const S*)cd.buf[b];
+    const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
     const __half* rb = cd.rbuf[b];
     const int64_t n = (int64_t)cd.nx * cd.ny;
     auto node = [&](int ux, int uy) -> int64_t {
@@ -312,10 +323,10 @@ __device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
     auto rf = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[node(ux, uy)])) : R(0); };
     auto rq = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[c.plane + node(ux, uy)])) : R(0); };
     auto none = [&](int, int) -> R { return R(0); };
-    export_set<SET_F>(c, src, x, y, out, n, rf(x, y), rf);
-    export_set<SET_G>(c, src, x, y, out, n, R(0), none);
-    export_set<SET_H>(c, src, x, y, out, n, REFS ? c.Tlaw(R(x)) : R(0), none);
-    export_set<SET_Q>(c, src, x, y, out, n, rq(x, y), rq);
+    export_set<SET_F, S>(c, src, x, y, out, n, rf(x, y), rf);
+    export_set<SET_G, S>(c, src, x, y, out, n, R(0), none);
+    export_set<SET_H, S>(c, src, x, y, out, n, REFS ? c.Tlaw(R(x)) : R(0), none);
+    export_set<SET_Q, S>(c, src, x, y, out, n, rq(x, y), rq);
 }
 
 __global__ void k_export(const CaseDev* __restrict__ cases, int case_id, int b, double* out)
@@ -410,6 +421,10 @@ int validate(const lbm_case& c, int i)
     if (c.nx < 4 || c.ny < 4) return fail(LBM_E_INVAL, "case %d: nx, ny must be >= 4", i);
     if ((int64_t)c.nx * c.ny > (int64_t)1 << 28) return fail(LBM_E_INVAL, "case %d: lattice too large", i);
     if (c.precision < 0 || c.precision > 2) return fail(LBM_E_INVAL, "case %d: precision", i);
+    // one population buffer (36 planes) is addressed with 32-bit byte offsets
+    if (case_pop_bytes(c) > (size_t)0xFFFFFF00u)
+        return fail(LBM_E_INVAL, "case %d: %dx%d needs %zu bytes per population buffer; the limit is 4 GiB", i, c.nx,
+                    c.ny, case_pop_bytes(c));
     if (c.sigma_law < 0 || c.sigma_law > 1) return fail(LBM_E_INVAL, "case %d: sigma_law", i);
     if (c.init_kind < 0 || c.init_kind > 2) return fail(LBM_E_INVAL, "case %d: init_kind", i);
     if (c.wall[0] != c.wall[1] || c.wall[2] != c.wall[3])
@@ -473,6 +488,8 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
     d.inv_scale = 1.0 / d.scale;
     d.plane = (int64_t)c.ny * d.pitch;
     d.max_steps = c.max_steps;
+    d.pop_bytes = (uint32_t)case_pop_bytes(c);
+    d.ref_bytes = (uint32_t)case_ref_bytes(c);
     d.buf[0] = b0;
     d.buf[1] = b1;
     d.rbuf[0] = (__half*)r0;
@@ -497,18 +514,28 @@ InitDev make_init(const lbm_case& c)
 
 using StepKernel = void (*)(const CaseDev*, const TileRec*, int, const int64_t*, int);
 
-template <typename R>
-StepKernel step_kernel(int shape)
+template <int ST>
+StepKernel step_kernel_st(int shape)
 {
     switch (shape) {
-        case 0: return k_step<R, 64, 8>;
-        case 1: return k_step<R, 64, 16>;
-        case 2: return k_step<R, 64, 32>;
-        case 3: return k_step<R, 32, 32>;
-        case 4: return k_step<R, 128, 8>;
-        case 5: return k_step<R, 128, 16>;
+        case 0: return k_step<ST, 64, 8>;
+        case 1: return k_step<ST, 64, 16>;
+        case 2: return k_step<ST, 64, 32>;
+        case 3: return k_step<ST, 32, 32>;
+        case 4: return k_step<ST, 128, 8>;
+        case 5: return k_step<ST, 128, 16>;
     }
     return nullptr;
+}
+
+StepKernel step_kernel(int st, int shape)
+{
+    switch (st) {
+        case ST_F64: return step_kernel_st<ST_F64>(shape);
+        case ST_F32: return step_kernel_st<ST_F32>(shape);
+        case ST_F16: return step_kernel_st<ST_F16>(shape);
+    }
+    return step_kernel_st<ST_MIXED>(shape);
 }
 
 // Tiles must fit the 64 KiB per-workgroup LDS budget (two workgroups per CU).
@@ -532,6 +559,7 @@ struct lbm_handle {
     char* ws = nullptr;
     Layout L{};
     bool fp64 = false;
+    int st = ST_F32;  // storage class of the step kernel
     int shape = 1;
     bool use_graph = true;
     bool timing = false;
@@ -548,7 +576,7 @@ struct lbm_handle {
 
     int launch_step(int t)
     {
-        StepKernel k = fp64 ? step_kernel<double>(shape) : step_kernel<float>(shape);
+        StepKernel k = step_kernel(st, shape);
         const int64_t nt = L.ntiles[shape];
         if (nt <= 0) return LBM_OK;
         hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream, d_cases(), d_tiles(shape), (int)nt,
@@ -667,6 +695,11 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
     h->ws = (char*)workspace;
     h->L = L;
     h->fp64 = any64;
+    {
+        bool a32 = false, a16 = false;
+        for (int i = 0; i < ncases; ++i) (cases[i].precision == LBM_FP16S ? a16 : a32) = true;
+        h->st = any64 ? ST_F64 : (a32 && a16 ? ST_MIXED : (a16 ? ST_F16 : ST_F32));
+    }
     h->steps.assign(ncases, 0);
     h->shape = shape_ok(1, h->fp64) ? 1 : 0;
 

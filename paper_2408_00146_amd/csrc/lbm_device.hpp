@@ -56,6 +56,8 @@ struct CaseDev {
     double scale, inv_scale;
     int64_t plane;      // elements per (set, dir) plane = ny * pitch
     int64_t max_steps;  // <= 0: unlimited
+    uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
+    uint32_t ref_bytes; // bytes of one reference buffer (2 FP16 planes)
     void* buf[2];       // ping-pong population buffers
     __half* rbuf[2];    // per-node references [2 = phi, psi][ny][pitch] of each buffer (refs only)
 };
@@ -69,7 +71,7 @@ template <typename R>
 struct Ctx {
     int nx, ny, pitch, wallx, wally, law;
     int tbc, pbc;  // bit s set: Dirichlet T / psi on side s (no dynamic array indexing: keeps Ctx in registers)
-    int64_t plane;
+    int plane;     // elements per plane; 36 planes fit a 4 GiB buffer resource
     const double* psi_w;  // wall values read from global memory (a select over struct fields would defeat SROA)
     R T0, gradT, xT0;
     R s0, sT, sTT, Tref, beta, inv_psi_inf;
@@ -83,7 +85,7 @@ struct Ctx {
     __device__ void load(const CaseDev& c)
     {
         nx = c.nx; ny = c.ny; pitch = c.pitch; wallx = c.wallx; wally = c.wally; law = c.law;
-        plane = c.plane;
+        plane = (int)c.plane;
         tbc = (c.tbc[0] ? 1 : 0) | (c.tbc[1] ? 2 : 0) | (c.tbc[2] ? 4 : 0) | (c.tbc[3] ? 8 : 0);
         pbc = (c.pbc[0] ? 1 : 0) | (c.pbc[1] ? 2 : 0) | (c.pbc[2] ? 4 : 0) | (c.pbc[3] ? 8 : 0);
         psi_w = c.psi_w;
@@ -123,6 +125,61 @@ __device__ __forceinline__ float enc<float, float>(float v, float) { return v; }
 template <>
 __device__ __forceinline__ __half enc<__half, float>(float v, float scale) { return __float2half_rn(v * scale); }
 
+// ------------------------------------------------------------ buffer access
+// Populations and references are read and written through buffer resources:
+// one 32-bit VGPR byte offset per node, shared by all directions, and one
+// scalar (SGPR) byte offset per (set, direction) -- no per-access 64-bit
+// address arithmetic.  Accesses outside the resource return 0 / are dropped.
+constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+
+template <typename S>
+struct Mem;
+template <>
+struct Mem<double> {
+    static __device__ __forceinline__ double ld(Rsrc r, uint32_t v, uint32_t s)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void st(double x, Rsrc r, uint32_t v, uint32_t s)
+    {
+        using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, x), r, v, s, 0);
+    }
+};
+template <>
+struct Mem<float> {
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t v, uint32_t s)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void st(float x, Rsrc r, uint32_t v, uint32_t s)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, 0);
+    }
+};
+template <>
+struct Mem<__half> {
+    static __device__ __forceinline__ __half ld(Rsrc r, uint32_t v, uint32_t s)
+    {
+        return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void st(__half x, Rsrc r, uint32_t v, uint32_t s)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(x), r, v, s, 0);
+    }
+};
+
+// A population buffer as seen by one tile.
+struct View {
+    Rsrc r;
+};
+
 // ----------------------------------------------------------- streaming
 // Post-streaming population X_a at node m (unwrapped tile coordinates u, in
 // the lattice after periodic wrapping m), relative to w_a * base, where base
@@ -134,46 +191,55 @@ __device__ __forceinline__ __half enc<__half, float>(float v, float scale) { ret
 // caller guarantees every source lies inside the lattice (no wrap, no wall).
 // RF(ux, uy) returns the per-node reference of set SET at unwrapped node u.
 template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
-__device__ __forceinline__ R pull(const Ctx<R>& c, const S* __restrict__ src, int ux, int uy, int mx, int my, R base,
-                                  const RF& rf)
+__device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf)
 {
     constexpr int EX = ex(A), EY = ey(A);
+    constexpr uint32_t E = sizeof(S);
     constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q);
     const R w = R(wt(A));
+    if (INT) {
+        // shift of the source folded into the scalar offset (never negative: plane >= pitch + 1)
+        const uint32_t v = (uint32_t)(my * c.pitch + mx) * E;
+        const uint32_t so = (uint32_t)((SET * 9 + A) * c.plane - EY * c.pitch - EX) * E;
+        R val = dec<S, R>(Mem<S>::ld(src.r, v, so), c.inv_scale);
+        if (NODE_REF) val += w * (rf(ux - EX, uy - EY) - base);
+        if (REFS && SET == SET_H && EX != 0) val -= w * c.gradT * R(EX);  // linear-law reference of column mx - ex
+        return val;
+    }
     int sx = mx - EX, sy = my - EY;
     bool wall = false;
     int side = 0;
-    if (!INT) {
-        if (EY != 0 && (sy < 0 || sy >= c.ny)) {
-            if (c.wally) { wall = true; side = sy < 0 ? 2 : 3; }
-            else sy += sy < 0 ? c.ny : -c.ny;
-        }
-        if (EX != 0 && !wall && (sx < 0 || sx >= c.nx)) {
-            if (c.wallx) { wall = true; side = sx < 0 ? 0 : 1; }
-            else sx += sx < 0 ? c.nx : -c.nx;
-        }
+    if (EY != 0 && (sy < 0 || sy >= c.ny)) {
+        if (c.wally) { wall = true; side = sy < 0 ? 2 : 3; }
+        else sy += sy < 0 ? c.ny : -c.ny;
+    }
+    if (EX != 0 && !wall && (sx < 0 || sx >= c.nx)) {
+        if (c.wallx) { wall = true; side = sx < 0 ? 0 : 1; }
+        else sx += sx < 0 ? c.nx : -c.nx;
     }
     if (!wall) {
-        R v = dec<S, R>(src[(int64_t)(SET * 9 + A) * c.plane + (int64_t)sy * c.pitch + sx], c.inv_scale);
-        if (NODE_REF) v += w * (rf(ux - EX, uy - EY) - base);
-        if (REFS && SET == SET_H && EX != 0) v += w * c.gradT * R(sx - mx);  // linear-law reference of column sx
-        return v;
+        R val = dec<S, R>(Mem<S>::ld(src.r, (uint32_t)(sy * c.pitch + sx) * E, (uint32_t)((SET * 9 + A) * c.plane) * E),
+                          c.inv_scale);
+        if (NODE_REF) val += w * (rf(ux - EX, uy - EY) - base);
+        if (REFS && SET == SET_H && EX != 0) val += w * c.gradT * R(sx - mx);  // linear-law reference of column sx
+        return val;
     }
     constexpr int B = opp(A);
-    R v = dec<S, R>(src[(int64_t)(SET * 9 + B) * c.plane + (int64_t)my * c.pitch + mx], c.inv_scale);
-    if (NODE_REF) v += w * (rf(ux, uy) - base);
+    R val = dec<S, R>(Mem<S>::ld(src.r, (uint32_t)(my * c.pitch + mx) * E, (uint32_t)((SET * 9 + B) * c.plane) * E),
+                      c.inv_scale);
+    if (NODE_REF) val += w * (rf(ux, uy) - base);
     if (SET == SET_H && c.t_dir(side)) {
         // X_w - base; with the linear-law reference exactly -gradT ex / 2
         const R d = REFS ? R(-0.5) * c.gradT * R(EX) : c.Tlaw(R(mx) - R(0.5) * R(EX)) - base;
-        return -v + R(2) * w * d;
+        return -val + R(2) * w * d;
     }
-    if (SET == SET_Q && c.p_dir(side)) return -v + R(2) * w * (c.psi_wall(side) - base);
-    return v;
+    if (SET == SET_Q && c.p_dir(side)) return -val + R(2) * w * (c.psi_wall(side) - base);
+    return val;
 }
 
 template <int SET, bool INT, bool REFS, typename S, typename R, typename RF>
-__device__ __forceinline__ void pull9(const Ctx<R>& c, const S* __restrict__ src, int ux, int uy, int mx, int my,
-                                      R base, const RF& rf, R v[9])
+__device__ __forceinline__ void pull9(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf,
+                                      R v[9])
 {
     v[0] = pull<SET, 0, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
     v[1] = pull<SET, 1, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
@@ -184,6 +250,15 @@ __device__ __forceinline__ void pull9(const Ctx<R>& c, const S* __restrict__ src
     v[6] = pull<SET, 6, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
     v[7] = pull<SET, 7, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
     v[8] = pull<SET, 8, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+}
+
+// Store the 9 post-collision populations of a set at node offset v (bytes).
+template <int SET, typename S, typename R>
+__device__ __forceinline__ void store9(const Ctx<R>& c, View dst, uint32_t v, const R x[9])
+{
+    constexpr uint32_t E = sizeof(S);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Mem<S>::st(enc<S, R>(x[a], c.scale), dst.r, v, (uint32_t)((SET * 9 + a) * c.plane) * E);
 }
 
 template <typename R>
@@ -380,8 +455,7 @@ __device__ __forceinline__ void grad2(const T* D, const T* B, int p, int W, T& g
 }
 
 template <typename R, typename S, int BX, int BY, int MODE, bool INT>
-__device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const S* __restrict__ src, S* __restrict__ dst,
-                                          const __half* __restrict__ rsrc, __half* __restrict__ rdst,
+__device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View src, View dst, Rsrc rsrc, Rsrc rdst,
                                           Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc)
 {
     constexpr bool REFS = sizeof(R) == 4;
@@ -389,7 +463,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     const int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
-    const int64_t rplane = c.plane;  // reference planes share the population pitch
+    const uint32_t rplane_b = (uint32_t)c.plane * 2u;  // reference planes share the population pitch
 
     // per-node references of the f and q sets at unwrapped tile coordinates
     auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
@@ -411,9 +485,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
                 int mx = wrapx(ux), my = wrapy(uy);
                 // beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
                 if (mx >= 0 && mx < c.nx && my >= 0 && my < c.ny) {
-                    const int64_t o = (int64_t)my * c.pitch + mx;
-                    a = R(__half2float(rsrc[o]));
-                    b = R(__half2float(rsrc[rplane + o]));
+                    const uint32_t ob = (uint32_t)(my * c.pitch + mx) * 2u;
+                    a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
+                    b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
                 }
             }
             sh.rf[k] = a;
@@ -433,18 +507,18 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
         if (ghostx(ux) || ghosty(uy) || (!INT && (mx < 0 || mx >= c.nx || my < 0 || my >= c.ny))) continue;
         R v[9];
         const R bf = ref_f(ux, uy);
-        pull9<SET_F, INT, REFS>(c, src, ux, uy, mx, my, bf, ref_f, v);
+        pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, v);
         sh.phd[k] = sum9(v);
         if (REFS) sh.phb[k] = bf;
         if (in1) {
-            pull9<SET_G, INT, REFS>(c, src, ux, uy, mx, my, R(0), no_ref, v);
+            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, R(0), no_ref, v);
             sh.ps[e1] = sum9(v);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
-            pull9<SET_H, INT, REFS>(c, src, ux, uy, mx, my, bh, no_ref, v);
+            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, v);
             // T - T_w(ux): with the linear-law reference exactly gradT (mx - ux) + sum
             sh.ts[e1] = REFS ? c.gradT * R(mx - ux) + sum9(v) : R((double)sum9(v) - c.Tlaw_d((double)ux));
             const R bq = ref_q(ux, uy);
-            pull9<SET_Q, INT, REFS>(c, src, ux, uy, mx, my, bq, ref_q, v);
+            pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, v);
             sh.pq[e1] = bq + sum9(v);
         }
     }
@@ -559,7 +633,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
 
         // g: momentum, velocity and pressure
         R g[9];
-        pull9<SET_G, INT, REFS>(c, src, x, y, x, y, R(0), no_ref, g);
+        pull9<SET_G, INT, REFS, S>(c, src, x, y, x, y, R(0), no_ref, g);
         const R jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
         const R jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
         const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
@@ -571,9 +645,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
 
         if (MODE == MODE_MACRO) {
             R hv[9], qv[9], fv[9];
-            pull9<SET_H, INT, REFS>(c, src, x, y, x, y, bh, no_ref, hv);
-            pull9<SET_Q, INT, REFS>(c, src, x, y, x, y, bq, ref_q, qv);
-            pull9<SET_F, INT, REFS>(c, src, x, y, x, y, phb, ref_f, fv);
+            pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hv);
+            pull9<SET_Q, INT, REFS, S>(c, src, x, y, x, y, bq, ref_q, qv);
+            pull9<SET_F, INT, REFS, S>(c, src, x, y, x, y, phb, ref_f, fv);
             const R T = bh + sum9(hv);
             const R psi = bq + sum9(qv);
             if (mo.fields) {
@@ -609,40 +683,36 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, const
             continue;
         }
 
-        const int64_t o = (int64_t)y * c.pitch + x;
+        const uint32_t o = (uint32_t)(y * c.pitch + x);
         collide_g(g, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_G * 9 + a) * c.plane + o] = enc<S, R>(g[a], c.scale);
+        store9<SET_G, S>(c, dst, o * (uint32_t)sizeof(S), g);
 
         // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
         // the new storage reference is the FP16-rounded phi of this node
         R f[9];
-        pull9<SET_F, INT, REFS>(c, src, x, y, x, y, phb, ref_f, f);
+        pull9<SET_F, INT, REFS, S>(c, src, x, y, x, y, phb, ref_f, f);
         const R mt = c.Mphi * R(4) * phi * omphi / c.W;
         const R nbf = REFS ? R(__half2float(__float2half_rn((float)phi))) : R(0);
         collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_F * 9 + a) * c.plane + o] = enc<S, R>(f[a], c.scale);
+        store9<SET_F, S>(c, dst, o * (uint32_t)sizeof(S), f);
 
         // h: temperature
         R hh[9];
-        pull9<SET_H, INT, REFS>(c, src, x, y, x, y, bh, no_ref, hh);
+        pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hh);
         collide_ad(hh, bh, bh, R(0), R(0), omT, ux, uy);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_H * 9 + a) * c.plane + o] = enc<S, R>(hh[a], c.scale);
+        store9<SET_H, S>(c, dst, o * (uint32_t)sizeof(S), hh);
 
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
         R qq[9];
-        pull9<SET_Q, INT, REFS>(c, src, x, y, x, y, bq, ref_q, qq);
+        pull9<SET_Q, INT, REFS, S>(c, src, x, y, x, y, bq, ref_q, qq);
         const R psi = bq + sum9(qq);
         const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
         const R nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
         collide_ad(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) dst[(int64_t)(SET_Q * 9 + a) * c.plane + o] = enc<S, R>(qq[a], c.scale);
+        store9<SET_Q, S>(c, dst, o * (uint32_t)sizeof(S), qq);
         if (REFS) {
-            rdst[o] = __float2half_rn((float)nbf);
-            rdst[rplane + o] = __float2half_rn((float)nbq);
+            Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
+            Mem<__half>::st(__float2half_rn((float)nbq), rdst, o * 2u, rplane_b);
         }
     }
 }

@@ -52,6 +52,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_2408_00146_amd/csrc/lbm.hip", "paper_2408_00146_amd/csrc/lbm_device.hpp", "include/lbm.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, shape) -> int | None:
+    """HBM bytes per step launch from the committed counter summary of this
+    workload and tile, or None when there is none or the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("tile") != f"{shape[0]}x{shape[1]}":
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(params: dict, budget_s: float = 15.0) -> dict:
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
@@ -73,8 +107,8 @@ def cpu_baseline(params: dict, budget_s: float = 15.0) -> dict:
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="fp32_1024x512x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -138,7 +172,8 @@ def main():
                    "grids": sorted({f"{p['nx']}x{p['ny']}" for p in ps}),
                    "tile": list(shape), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.workload, shape),
                      "kernel": "k_step", "avg_launch_ms": round(kms, 5), "launches": nlaunch,
                      "alg_bytes_per_launch": alg_bytes},
     }

@@ -157,14 +157,24 @@ int lbm_load_fields(lbm_handle* h, int32_t case_id, const void* phi, const void*
  * LBM_E_NONFINITE when any population is NaN/Inf; *out is filled either way. */
 int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
 
-/* Tile-shape selection.  lbm_autotune times every compiled tile shape on this
- * handle's cases (a trial step re-reads the current state and writes only the
- * scratch half of the ping-pong pair, so the state is unchanged) and keeps the
- * fastest; it synchronizes.  lbm_set_tile picks one by index (see
- * lbm_tile_count / lbm_tile_shape). */
+/* Step-kernel configuration.  Index i < lbm_tile_count() selects either
+ *   kind 0: one workgroup per bx x by tile (tile plus halo staged per step), or
+ *   kind 1: strip marching: one workgroup per strip of bx = 62 columns and
+ *           segment of by rows, marching 4 rows per iteration with the
+ *           reduced fields of the rows in flight kept in LDS ring buffers;
+ *           cases with nx < 70 or ny < 16 are advanced by the tile kernel of
+ *           configuration 0 in the same step.
+ * Every configuration computes the same step (results agree to rounding of
+ * identical operations).  lbm_autotune times every configuration valid for
+ * this handle's cases (a trial step re-reads the current state and writes
+ * only the scratch half of the ping-pong pair, so the state is unchanged)
+ * and keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
+ * lbm_tile_shape / lbm_tile_kind describe an index (LBM_E_INVAL if out of
+ * range).  A new handle starts with configuration 0 (64 x 8 tiles). */
 int lbm_autotune(lbm_handle* h, int32_t trial_steps);
 int lbm_tile_count(void);
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by);
+int lbm_tile_kind(int32_t index);
 int lbm_set_tile(lbm_handle* h, int32_t index);
 int lbm_get_tile(lbm_handle* h);
 
@@ -175,10 +185,11 @@ int lbm_set_graph(lbm_handle* h, int32_t enable);
 /* Steps done by one case. */
 int64_t lbm_steps_done(lbm_handle* h, int32_t case_id);
 
-/* Average duration (ms) of the step kernel over the launches of the last
- * lbm_step call made while timing was on, measured with HIP events on the
- * handle's stream (timing forces plain launches).  Returns LBM_E_STATE when
- * no timed launch exists. */
+/* Average duration (ms) of one step's kernel launches (the step kernel, and
+ * for strip configurations the tile kernel of the cases too small for
+ * strips) over the steps of the last lbm_step call made while timing was on,
+ * measured with HIP events on the handle's stream around each step (timing
+ * forces plain launches).  Returns LBM_E_STATE when no timed step exists. */
 int lbm_set_kernel_timing(lbm_handle* h, int32_t enable);
 int lbm_kernel_time_ms(lbm_handle* h, double* avg_ms, int64_t* launches);
 

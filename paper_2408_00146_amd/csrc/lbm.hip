@@ -24,6 +24,20 @@ struct Shape {
 constexpr Shape kShapes[] = {{64, 8}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMacroBX = 64, kMacroBY = 8;
+// Strip-marching configurations: kStripBY rows per iteration (64 x kStripBY
+// threads), segments of kStripSY[j] rows.  Cases narrower than kStripMinNx or
+// lower than kStripMinNy (whose strip halos would wrap more than once) are
+// advanced by the tile kernel of shape 0 in the same step.
+constexpr int kStripBY = 4;
+struct StripCfg {
+    int sy;    // segment rows
+    bool reg;  // populations kept in registers between pull and collision
+};
+constexpr StripCfg kStripCfg[] = {{16, false}, {24, false}, {32, false}, {48, false}, {64, false},
+                                  {16, true},  {24, true},  {32, true},  {48, true},  {64, true}};
+constexpr int kNumStrip = sizeof(kStripCfg) / sizeof(kStripCfg[0]);
+constexpr int kNumConfigs = kNumShapes + kNumStrip;
+constexpr int kStripMinNx = kStripW + 8, kStripMinNy = 16;
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
 // Remap so that each XCD walks one contiguous band of the tile table: the
@@ -82,6 +96,35 @@ __global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases,
     } else {
         if (cd.prec == PREC_FP16S) run_tile<float, __half, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
         else run_tile<float, float, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+    }
+}
+
+template <int ST, int BY, bool REG>
+__global__ __launch_bounds__(64 * BY) void k_strip(const CaseDev* __restrict__ cases, const StripRec* __restrict__ units,
+                                                   int nunits, const int64_t* __restrict__ steps, int t)
+{
+    using R = typename std::conditional<ST == ST_F64, double, float>::type;
+    __shared__ StripSmem<R, BY, sizeof(R) == 4> sh;
+    const StripRec u = units[xcd_remap(blockIdx.x, nunits)];
+    const CaseDev& cd = cases[u.c];
+    const int64_t s = steps[u.c] + t;
+    if (cd.max_steps > 0 && s >= cd.max_steps) return;  // uniform over the block
+    Ctx<R> c;
+    c.load(cd);
+    const int b = (int)(s & 1);
+    const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
+    const View dst{make_rsrc(cd.buf[b ^ 1], cd.pop_bytes)};
+    const Rsrc rsrc = make_rsrc(cd.rbuf[b], cd.ref_bytes);
+    const Rsrc rdst = make_rsrc(cd.rbuf[b ^ 1], cd.ref_bytes);
+    if constexpr (ST == ST_F64) {
+        strip_body<double, double, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
+    } else if constexpr (ST == ST_F32) {
+        strip_body<float, float, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
+    } else if constexpr (ST == ST_F16) {
+        strip_body<float, __half, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
+    } else {
+        if (cd.prec == PREC_FP16S) strip_body<float, __half, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
+        else strip_body<float, float, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
     }
 }
 
@@ -376,9 +419,14 @@ size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : 
 
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
 
+bool strip_ok(const lbm_case& c) { return c.nx >= kStripMinNx && c.ny >= kStripMinNy; }
+
+int64_t strips_of(const lbm_case& c, int sy) { return strip_ok(c) ? (int64_t)((c.nx + kStripW - 1) / kStripW) * ((c.ny + sy - 1) / sy) : 0; }
+
 struct Layout {
-    size_t off_cases, off_steps, off_partials, off_diag, off_tiles[kNumShapes], off_mtiles, off_pops, total;
-    int64_t ntiles[kNumShapes], nmtiles, max_case_mtiles;
+    size_t off_cases, off_steps, off_partials, off_diag, off_tiles[kNumShapes], off_strips[kNumStrip], off_rest, off_mtiles,
+        off_pops, total;
+    int64_t ntiles[kNumShapes], nstrips[kNumStrip], nrest, nmtiles, max_case_mtiles;
 };
 
 Layout layout_of(const lbm_case* cs, int n)
@@ -406,6 +454,21 @@ Layout layout_of(const lbm_case* cs, int n)
         for (int i = 0; i < n; ++i) t += tiles_of(cs[i], kShapes[s].bx, kShapes[s].by);
         L.ntiles[s] = t;
         L.off_tiles[s] = o;
+        o = align256(o + sizeof(TileRec) * (size_t)t);
+    }
+    for (int j = 0; j < kNumStrip; ++j) {
+        int64_t t = 0;
+        for (int i = 0; i < n; ++i) t += strips_of(cs[i], kStripCfg[j].sy);
+        L.nstrips[j] = t;
+        L.off_strips[j] = o;
+        o = align256(o + sizeof(StripRec) * (size_t)t);
+    }
+    {
+        int64_t t = 0;
+        for (int i = 0; i < n; ++i)
+            if (!strip_ok(cs[i])) t += tiles_of(cs[i], kShapes[0].bx, kShapes[0].by);
+        L.nrest = t;
+        L.off_rest = o;
         o = align256(o + sizeof(TileRec) * (size_t)t);
     }
     L.off_mtiles = o;
@@ -538,6 +601,21 @@ StepKernel step_kernel(int st, int shape)
     return step_kernel_st<ST_MIXED>(shape);
 }
 
+using StripKernel = void (*)(const CaseDev*, const StripRec*, int, const int64_t*, int);
+
+template <bool REG>
+StripKernel strip_kernel_reg(int st)
+{
+    switch (st) {
+        case ST_F64: return k_strip<ST_F64, kStripBY, REG>;
+        case ST_F32: return k_strip<ST_F32, kStripBY, REG>;
+        case ST_F16: return k_strip<ST_F16, kStripBY, REG>;
+    }
+    return k_strip<ST_MIXED, kStripBY, REG>;
+}
+
+StripKernel strip_kernel(int st, bool reg) { return reg ? strip_kernel_reg<true>(st) : strip_kernel_reg<false>(st); }
+
 // Tiles must fit the 64 KiB per-workgroup LDS budget (two workgroups per CU).
 bool shape_ok(int shape, bool fp64)
 {
@@ -545,6 +623,13 @@ bool shape_ok(int shape, bool fp64)
     const size_t e3 = fp64 ? 0 : (size_t)(bx + 6) * (by + 6), e2 = (size_t)(bx + 4) * (by + 4), e1 = (size_t)(bx + 2) * (by + 2);
     const size_t lds = (2 * e3 + (fp64 ? 1 : 2) * e2 + 5 * e1) * (fp64 ? 8 : 4) + 8 * e1;
     return lds <= 65536;
+}
+
+// Step configuration: tile shape (index < kNumShapes) or strip segment length.
+bool config_ok(int cfg, bool fp64)
+{
+    if (cfg < 0 || cfg >= kNumConfigs) return false;
+    return cfg >= kNumShapes || shape_ok(cfg, fp64);
 }
 
 }  // namespace
@@ -574,14 +659,30 @@ struct lbm_handle {
     TileRec* d_tiles(int s) { return (TileRec*)(ws + L.off_tiles[s]); }
     TileRec* d_mtiles() { return (TileRec*)(ws + L.off_mtiles); }
 
+    StripRec* d_strips(int j) { return (StripRec*)(ws + L.off_strips[j]); }
+    TileRec* d_rest() { return (TileRec*)(ws + L.off_rest); }
+
     int launch_step(int t)
     {
-        StepKernel k = step_kernel(st, shape);
-        const int64_t nt = L.ntiles[shape];
-        if (nt <= 0) return LBM_OK;
-        hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream, d_cases(), d_tiles(shape), (int)nt,
-                           d_steps(), t);
-        HIPCHK(hipGetLastError());
+        if (shape < kNumShapes) {
+            const int64_t nt = L.ntiles[shape];
+            if (nt <= 0) return LBM_OK;
+            hipLaunchKernelGGL(step_kernel(st, shape), dim3((unsigned)nt), dim3(256), 0, stream, d_cases(),
+                               d_tiles(shape), (int)nt, d_steps(), t);
+            HIPCHK(hipGetLastError());
+            return LBM_OK;
+        }
+        const int j = shape - kNumShapes;
+        if (L.nstrips[j] > 0) {
+            hipLaunchKernelGGL(strip_kernel(st, kStripCfg[j].reg), dim3((unsigned)L.nstrips[j]), dim3(64 * kStripBY), 0, stream,
+                               d_cases(), d_strips(j), (int)L.nstrips[j], d_steps(), t);
+            HIPCHK(hipGetLastError());
+        }
+        if (L.nrest > 0) {
+            hipLaunchKernelGGL(step_kernel(st, 0), dim3((unsigned)L.nrest), dim3(256), 0, stream, d_cases(), d_rest(),
+                               (int)L.nrest, d_steps(), t);
+            HIPCHK(hipGetLastError());
+        }
         return LBM_OK;
     }
     int launch_advance(int64_t k)
@@ -701,7 +802,7 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         h->st = any64 ? ST_F64 : (a32 && a16 ? ST_MIXED : (a16 ? ST_F16 : ST_F32));
     }
     h->steps.assign(ncases, 0);
-    h->shape = shape_ok(1, h->fp64) ? 1 : 0;
+    h->shape = 0;  // 64 x 8 tiles
 
     size_t o = L.off_pops;
     for (int i = 0; i < ncases; ++i) {
@@ -724,6 +825,29 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
             for (int y = 0; y < cases[i].ny; y += kShapes[s].by)
                 for (int x = 0; x < cases[i].nx; x += kShapes[s].bx) tiles.push_back(TileRec{i, x, y, 0});
         rc = upload(h->d_tiles(s));
+    }
+    for (int j = 0; j < kNumStrip && rc == LBM_OK; ++j) {
+        std::vector<StripRec> st;
+        for (int i = 0; i < ncases; ++i) {
+            if (!strip_ok(cases[i])) continue;
+            const int sy = kStripCfg[j].sy;
+            for (int y = 0; y < cases[i].ny; y += sy)
+                for (int x = 0; x < cases[i].nx; x += kStripW) st.push_back(StripRec{i, x, y, std::min(y + sy, cases[i].ny)});
+        }
+        if (!st.empty()) {
+            hipError_t e = hipMemcpyAsync(h->d_strips(j), st.data(), st.size() * sizeof(StripRec), hipMemcpyHostToDevice,
+                                          h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "strip table upload: %s", hipGetErrorString(e));
+        }
+    }
+    if (rc == LBM_OK) {
+        tiles.clear();
+        for (int i = 0; i < ncases; ++i)
+            if (!strip_ok(cases[i]))
+                for (int y = 0; y < cases[i].ny; y += kShapes[0].by)
+                    for (int x = 0; x < cases[i].nx; x += kShapes[0].bx) tiles.push_back(TileRec{i, x, y, 0});
+        rc = upload(h->d_rest());
     }
     if (rc == LBM_OK) {
         tiles.clear();
@@ -770,19 +894,24 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
         for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
         h->ev.clear();
         h->timed = 0;
-        for (int64_t t = 0; t < nsteps; ++t) {
-            hipEvent_t a, b;
-            HIPCHK(hipEventCreate(&a));
-            HIPCHK(hipEventCreate(&b));
-            h->ev.push_back(a);
-            h->ev.push_back(b);
-            HIPCHK(hipEventRecord(a, h->stream));
-            int rc = h->launch_step(0);
+        // eager launches bracketed by events; the step counters advance once per chunk
+        const int64_t CHT = 1000;
+        for (int64_t c0 = 0; c0 < nsteps; c0 += CHT) {
+            const int k = (int)std::min(nsteps - c0, CHT);
+            for (int t = 0; t < k; ++t) {
+                hipEvent_t a, b;
+                HIPCHK(hipEventCreate(&a));
+                HIPCHK(hipEventCreate(&b));
+                h->ev.push_back(a);
+                h->ev.push_back(b);
+                HIPCHK(hipEventRecord(a, h->stream));
+                int rc = h->launch_step(t);
+                if (rc != LBM_OK) return rc;
+                HIPCHK(hipEventRecord(b, h->stream));
+            }
+            int rc = h->launch_advance(k);
             if (rc != LBM_OK) return rc;
-            HIPCHK(hipEventRecord(b, h->stream));
-            rc = h->launch_advance(1);
-            if (rc != LBM_OK) return rc;
-            h->host_advance(1);
+            h->host_advance(k);
         }
         h->timed = nsteps;
         return LBM_OK;
@@ -954,21 +1083,28 @@ int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out)
     return LBM_OK;
 }
 
-int lbm_tile_count(void) { return kNumShapes; }
+int lbm_tile_count(void) { return kNumConfigs; }
 
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by)
 {
-    if (index < 0 || index >= kNumShapes) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    if (bx) *bx = kShapes[index].bx;
-    if (by) *by = kShapes[index].by;
+    if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
+    const bool strip = index >= kNumShapes;
+    if (bx) *bx = strip ? kStripW : kShapes[index].bx;
+    if (by) *by = strip ? kStripCfg[index - kNumShapes].sy : kShapes[index].by;
     return LBM_OK;
+}
+
+int lbm_tile_kind(int32_t index)
+{
+    if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
+    return index >= kNumShapes ? 1 : 0;
 }
 
 int lbm_set_tile(lbm_handle* h, int32_t index)
 {
     CHECK_H(h);
-    if (index < 0 || index >= kNumShapes) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    if (!shape_ok(index, h->fp64)) return fail(LBM_E_INVAL, "tile %d exceeds the LDS budget for FP64", index);
+    if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
+    if (!config_ok(index, h->fp64)) return fail(LBM_E_INVAL, "tile %d exceeds the LDS budget for FP64", index);
     if (index != h->shape) h->drop_graphs();
     h->shape = index;
     return LBM_OK;
@@ -991,8 +1127,8 @@ int lbm_autotune(lbm_handle* h, int32_t trial_steps)
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     int rc = LBM_OK;
-    for (int s = 0; s < kNumShapes && rc == LBM_OK; ++s) {
-        if (!shape_ok(s, h->fp64)) continue;
+    for (int s = 0; s < kNumConfigs && rc == LBM_OK; ++s) {
+        if (!config_ok(s, h->fp64)) continue;
         h->shape = s;
         // t = 0 every time: each trial re-reads the current state and rewrites
         // the scratch half of the ping-pong pair, leaving the state unchanged.

@@ -461,7 +461,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr bool REFS = sizeof(R) == 4;
     constexpr int NT = 256;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
     const uint32_t rplane_b = (uint32_t)c.plane * 2u;  // reference planes share the population pitch
 
@@ -497,6 +497,8 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     }
 
     // ---- phase 1a: phi on tile + 2 halo; p*, T, psi on tile + 1 halo (lattice nodes)
+    // (tid is made opaque at each phase so that no index math is kept live across phases)
+    asm volatile("" : "+v"(tid));
     for (int k = tid; k < W2 * H2; k += NT) {
         const int lx = k % W2, ly = k / W2;
         const int ux = x0 - 2 + lx, uy = y0 - 2 + ly;
@@ -568,6 +570,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     }
 
     // ---- phase 2: unit normal n = grad phi / |grad phi| and sigma(T, psi) on tile + 1 halo
+    asm volatile("" : "+v"(tid));
     for (int e = tid; e < W1 * H1; e += NT) {
         const int lx = e % W1 + 1, ly = e / W1 + 1;  // E2 coordinates
         R gx, gy;
@@ -583,6 +586,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
 
     // ---- phase 3: own nodes
     constexpr int ROWS = NT / BX;  // rows covered by the block per pass
+    asm volatile("" : "+v"(tid));
     const int lx = tid % BX;
     for (int ly = tid / BX; ly < BY; ly += ROWS) {
         const int x = x0 + lx, y = y0 + ly;
@@ -714,6 +718,457 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
             Mem<__half>::st(__float2half_rn((float)nbq), rdst, o * 2u, rplane_b);
         }
+    }
+}
+
+// ------------------------------------------------------------ strip marching
+// A workgroup of 64 x BY threads owns a strip of kStripW = 62 columns and a
+// segment [y0, y1) of rows, and marches up the segment BY rows per
+// iteration.  The reduced fields (phi; p*, T, psi; normal, sigma; storage
+// references) of the rows still needed live in LDS ring buffers (row r in
+// slot r mod RING), so each population is pulled about once per step
+// instead of once per overlapping tile halo, and each node keeps its 36
+// pulled populations in registers from the pull to its collision.
+// Wave j handles row y + j; lane l covers column x0 - 1 + l: lanes 1..62
+// own a node, lanes 0 and 63 compute the one-node x halo of the moments.
+// Per iteration (base row y):
+//   B  pull rows y .. y+BY-1 (registers; phi of rows >= y+2 and p*, T, psi
+//      of rows >= y+1 into the rings) and the halo slots: phi of rows
+//      y+BY, y+BY+1 and of the 2-node x halo, p*, T, psi of row y+BY;
+//   B2 (strips touching a wall) ghost nodes from their mirror nodes;
+//   C  normal and sigma of rows y+1 .. y+BY; storage references of the next
+//      iteration's rows;
+//   D  collide rows y .. y+BY-1 and store.
+// With RING >= 2 BY + 4 the writes of B and C never touch rows that the
+// previous D still reads, so an iteration needs two barriers.
+struct StripRec {
+    int32_t c, x0, y0, y1;
+};
+
+constexpr int kStripW = 62;
+
+template <typename R, int BY, bool REFS>
+struct StripSmem {
+    static constexpr int RING = 4 * BY;
+    static constexpr int W3 = kStripW + 6, W2 = kStripW + 4, W1 = kStripW + 2;
+    R rf[REFS ? RING * W3 : 1];  // phi reference
+    R rq[REFS ? RING * W3 : 1];  // psi reference
+    R phd[RING * W2];            // phi deviation from its reference
+    R phb[REFS ? RING * W2 : 1];
+    double sg[RING * W1];        // sigma (FP64)
+    R ps[RING * W1];             // p*
+    R ts[RING * W1];             // T - T_w(column)
+    R pq[RING * W1];             // psi
+    R nx[RING * W1];
+    R ny[RING * W1];
+};
+
+// Isotropic gradient (Sec. 3) on ring rows rm (y-1), r0 (y), rp (y+1) at
+// column cc; same operation order as grad2.
+template <typename R, bool REFS, typename T = R>
+__device__ __forceinline__ void grad_ring(const T* D, const T* B, int rm, int r0, int rp, int cc, T& gx, T& gy)
+{
+    T dx = T(4) * (D[r0 + cc + 1] - D[r0 + cc - 1]) + (D[rp + cc + 1] - D[rp + cc - 1]) + (D[rm + cc + 1] - D[rm + cc - 1]);
+    T dy = T(4) * (D[rp + cc] - D[rm + cc]) + (D[rp + cc + 1] - D[rm + cc + 1]) + (D[rp + cc - 1] - D[rm + cc - 1]);
+    if (REFS) {
+        dx += T(4) * (B[r0 + cc + 1] - B[r0 + cc - 1]) + (B[rp + cc + 1] - B[rp + cc - 1]) + (B[rm + cc + 1] - B[rm + cc - 1]);
+        dy += T(4) * (B[rp + cc] - B[rm + cc]) + (B[rp + cc + 1] - B[rm + cc + 1]) + (B[rp + cc - 1] - B[rm + cc - 1]);
+    }
+    gx = dx * T(1.0 / 12.0);
+    gy = dy * T(1.0 / 12.0);
+}
+
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
+// REG = true: each node's populations stay in registers from B to D;
+// REG = false: B only reduces moments (rows spread evenly over the waves) and
+// D pulls each set again (from cache) right before its collision.
+template <typename R, typename S, int BY, bool REG>
+__device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, View src, View dst, Rsrc rsrc,
+                                           Rsrc rdst, StripSmem<R, BY, sizeof(R) == 4>& sh)
+{
+    static_assert(REG || BY == 4, "the moment-only row mapping is written for 4 rows per iteration");
+    constexpr bool REFS = sizeof(R) == 4;
+    using SM = StripSmem<R, BY, REFS>;
+    constexpr int M = SM::RING - 1, W3 = SM::W3, W2 = SM::W2, W1 = SM::W1;
+    constexpr int NT = 64 * BY;
+    int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int x0 = u.x0, y0 = u.y0, y1 = u.y1;
+    const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
+    const uint32_t rplane_b = (uint32_t)c.plane * 2u;
+
+    auto i3 = [&](int ux, int uy) { return (uy & M) * W3 + (ux - x0 + 3); };
+    auto i2 = [&](int ux, int uy) { return (uy & M) * W2 + (ux - x0 + 2); };
+    auto i1 = [&](int ux, int uy) { return (uy & M) * W1 + (ux - x0 + 1); };
+    auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[i3(ux, uy)] : R(0); };
+    auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[i3(ux, uy)] : R(0); };
+    auto no_ref = [&](int, int) -> R { return R(0); };
+    // lattice node of an unwrapped coordinate (overhangs are shorter than the lattice)
+    auto wrapx = [&](int v) { return c.wallx ? v : (v < 0 ? v + c.nx : (v >= c.nx ? v - c.nx : v)); };
+    auto wrapy = [&](int v) { return c.wally ? v : (v < 0 ? v + c.ny : (v >= c.ny ? v - c.ny : v)); };
+    auto ghostx = [&](int v) { return c.wallx && (v < 0 || v >= c.nx); };
+    auto ghosty = [&](int v) { return c.wally && (v < 0 || v >= c.ny); };
+    // every pull of x0-3 .. x0+64 stays inside the lattice (no wrap, no wall)
+    const bool xint = x0 >= 3 && x0 + kStripW + 2 < c.nx;
+
+    // storage references of rows ra .. rb
+    auto load_refs = [&](int ra, int rb) {
+        if (!REFS) return;
+        const int n = (rb - ra + 1) * W3;
+        for (int k = tid; k < n; k += NT) {
+            const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
+            R a = R(0), b = R(0);
+            if (!ghostx(ux) && !ghosty(uy)) {
+                const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
+                a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
+                b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
+            }
+            const int e = i3(ux, uy);
+            sh.rf[e] = a;
+            sh.rq[e] = b;
+        }
+    };
+
+    // the same for the next iteration's rows, split into issue and commit so
+    // that the loads are in flight during the normals (at most 2 slots per thread)
+    static_assert(BY * W3 <= 2 * NT, "reference prefetch holds two slots per thread");
+    auto ref_fetch = [&](int ra, int k, R& a, R& b) {
+        a = R(0);
+        b = R(0);
+        if (!REFS || k >= BY * W3) return;
+        const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
+        if (!ghostx(ux) && !ghosty(uy)) {
+            const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
+            a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
+            b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
+        }
+    };
+    auto ref_put = [&](int ra, int k, R a, R b) {
+        if (!REFS || k >= BY * W3) return;
+        const int e = i3(x0 - 3 + k % W3, ra + k / W3);
+        sh.rf[e] = a;
+        sh.rq[e] = b;
+    };
+
+    // p*, T, psi of the node at unwrapped (ux, uy) into the rings (ghosts: zeros)
+    auto moments_e1 = [&](auto intc, int ux, int uy) {
+        constexpr bool INT = decltype(intc)::value;
+        const bool gh = !INT && (ghostx(ux) || ghosty(uy));
+        const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
+        R v[9];
+        R pv = R(0), tv = R(0), qv = R(0);
+        if (!gh) {
+            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, R(0), no_ref, v);
+            pv = sum9(v);
+            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, v);
+            tv = REFS ? c.gradT * R(mx - ux) + sum9(v) : R((double)sum9(v) - c.Tlaw_d((double)ux));
+            const R bq = ref_q(ux, uy);
+            pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, v);
+            qv = bq + sum9(v);
+        }
+        const int e = i1(ux, uy);
+        sh.ps[e] = pv;
+        sh.ts[e] = tv;
+        sh.pq[e] = qv;
+    };
+
+    // phi and (e1) p*, T, psi of the node at unwrapped (ux, uy) into the rings;
+    // ghost nodes get zeros here and their mirror values in B2
+    auto moments = [&](auto intc, int ux, int uy, bool e1) {
+        constexpr bool INT = decltype(intc)::value;
+        const bool gh = !INT && (ghostx(ux) || ghosty(uy));
+        const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
+        R v[9];
+        const R bf = ref_f(ux, uy);
+        R d = R(0);
+        if (!gh) {
+            pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, v);
+            d = sum9(v);
+        }
+        const int e2 = i2(ux, uy);
+        sh.phd[e2] = d;
+        if (REFS) sh.phb[e2] = gh ? R(0) : bf;
+        if (e1) moments_e1(intc, ux, uy);
+    };
+
+    // populations of the wave's row, kept in registers until the collision
+    R F[9], G[9], H[9], Q[9];
+    auto own_pulls = [&](auto intc, int y) {
+        constexpr bool INT = decltype(intc)::value;
+        const int ux = x0 - 1 + lane, uy = y + wv;
+        const bool gh = !INT && (ghostx(ux) || ghosty(uy));
+        const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
+        const R bf = ref_f(ux, uy), bq = ref_q(ux, uy);
+        const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+        if (!gh) {
+            pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, F);
+            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, R(0), no_ref, G);
+            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, H);
+            pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) F[a] = G[a] = H[a] = Q[a] = R(0);
+        }
+        if (wv >= 2) {
+            const int e2 = i2(ux, uy);
+            sh.phd[e2] = gh ? R(0) : sum9(F);
+            if (REFS) sh.phb[e2] = gh ? R(0) : bf;
+        }
+        if (wv >= 1) {
+            const int e = i1(ux, uy);
+            sh.ps[e] = gh ? R(0) : sum9(G);
+            sh.ts[e] = gh ? R(0) : (REFS ? c.gradT * R(mx - ux) + sum9(H) : R((double)sum9(H) - c.Tlaw_d((double)ux)));
+            sh.pq[e] = gh ? R(0) : bq + sum9(Q);
+        }
+    };
+
+    // halo slots of iteration y: phi of rows y+BY+1 and y+BY (66 columns each;
+    // p*, T, psi too on the 64 E1 columns of row y+BY) and phi of the columns
+    // x0-2, x0+63 of rows y+2 .. y+BY-1; spread evenly over the waves
+    auto halo_pulls = [&](auto intc, int y) {
+        constexpr int NH = 2 * W2 + 2 * (BY - 2), CH = (NH + BY - 1) / BY;
+        const int k = wv * CH + lane;
+        if (lane >= CH || k >= NH) return;
+        int ux, uy;
+        bool e1 = false;
+        if (k < W2) {
+            uy = y + BY + 1;
+            ux = x0 - 2 + k;
+        } else if (k < 2 * W2) {
+            const int col = k - W2;
+            uy = y + BY;
+            ux = x0 - 2 + col;
+            e1 = col >= 1 && col <= W1;
+        } else {
+            const int m = k - 2 * W2;
+            uy = y + 2 + (m >> 1);
+            ux = (m & 1) ? x0 + kStripW + 1 : x0 - 2;
+        }
+        moments(intc, ux, uy, e1);
+    };
+
+    // B without registers: wave 0 row y+4 (phi, p*, T, psi), wave 1 row y+1
+    // (p*, T, psi) and row y+5 (phi), waves 2, 3 rows y+2, y+3 (phi, p*, T,
+    // psi), all on the 64 E1 columns; lanes 0 and 63 of wave j add phi of
+    // columns x0-2 and x0+63 on row y+2+j
+    auto moment_rows = [&](auto intc, int y) {
+        const int ux = x0 - 1 + lane;
+        if (wv == 0) {
+            moments(intc, ux, y + 4, true);
+        } else if (wv == 1) {
+            moments_e1(intc, ux, y + 1);
+            moments(intc, ux, y + 5, false);
+        } else {
+            moments(intc, ux, y + wv, true);
+        }
+        if (lane == 0) moments(intc, x0 - 2, y + 2 + wv, false);
+        if (lane == 63) moments(intc, x0 + kStripW + 1, y + 2 + wv, false);
+    };
+
+    // before the first iteration: phi of rows y0-2 .. y0+1, p*, T, psi of rows y0-1 .. y0
+    auto prologue = [&](auto intc) {
+        for (int k = tid; k < 4 * W2; k += NT) {
+            const int col = k % W2, uy = y0 - 2 + k / W2;
+            moments(intc, x0 - 2 + col, uy, uy >= y0 - 1 && col >= 1 && col <= W1);
+        }
+    };
+
+    // ghost nodes beyond walls: the mirror node's value (zero normal
+    // gradient) or 2 X_w - X(mirror) for Dirichlet T / psi; phi on rows
+    // pa .. pb, p*, T, psi on rows ea .. eb
+    auto ghost_fill = [&](int pa, int pb, int ea, int eb) {
+        const int ra = pa < ea ? pa : ea, rb = pb > eb ? pb : eb;
+        const int n = (rb - ra + 1) * W2;
+        for (int k = tid; k < n; k += NT) {
+            const int col = k % W2, uy = ra + k / W2, ux = x0 - 2 + col;
+            const bool gx = ghostx(ux), gy = ghosty(uy);
+            if (!gx && !gy) continue;
+            // ghosts more than two nodes beyond a wall are read by no live node
+            if ((gx && (ux < -2 || ux > c.nx + 1)) || (gy && (uy < -2 || uy > c.ny + 1))) continue;
+            int xs = -1, ys = -1, mx = wrapx(ux), my = wrapy(uy);
+            if (gx) { xs = ux < 0 ? 0 : 1; mx = ux < 0 ? -1 - ux : 2 * c.nx - 1 - ux; }
+            if (gy) { ys = uy < 0 ? 2 : 3; my = uy < 0 ? -1 - uy : 2 * c.ny - 1 - uy; }
+            const int mux = gx ? mx : ux, muy = gy ? my : uy;
+            if (uy >= pa && uy <= pb) {
+                const int e = i2(ux, uy), m = i2(mux, muy);
+                sh.phd[e] = sh.phd[m];
+                if (REFS) sh.phb[e] = sh.phb[m];
+            }
+            const int mc = mux - x0 + 1;
+            if (uy >= ea && uy <= eb && col >= 1 && col <= W1 && mc >= 0 && mc < W1) {
+                const int e = i1(ux, uy), m = i1(mux, muy);
+                sh.ps[e] = sh.ps[m];
+                double T = c.Tlaw_d((double)mux) + (double)sh.ts[m];
+                R q = sh.pq[m];
+                if (ys >= 0 && c.t_dir(ys)) T = 2.0 * c.Tlaw_d((double)mx) - T;
+                if (xs >= 0 && c.t_dir(xs)) T = 2.0 * c.Tlaw_d(xs ? c.nx - 0.5 : -0.5) - T;
+                if (ys >= 0 && c.p_dir(ys)) q = R(2) * c.psi_wall(ys) - q;
+                if (xs >= 0 && c.p_dir(xs)) q = R(2) * c.psi_wall(xs) - q;
+                sh.ts[e] = R(T - c.Tlaw_d((double)ux));
+                sh.pq[e] = q;
+            }
+        }
+    };
+
+    // unit normal and sigma(T, psi) of rows ra .. rb (one row per wave)
+    auto normals = [&](int ra, int rb) {
+        for (int uy = ra + wv; uy <= rb; uy += BY) {
+            const int ux = x0 - 1 + lane;
+            R gx, gy;
+            grad_ring<R, REFS>(sh.phd, sh.phb, ((uy - 1) & M) * W2, (uy & M) * W2, ((uy + 1) & M) * W2, lane + 1, gx, gy);
+            R mag = sqrt(gx * gx + gy * gy);
+            mag = mag < R(1e-12) ? R(1e-12) : mag;
+            const int e = (uy & M) * W1 + lane;
+            sh.nx[e] = gx / mag;
+            sh.ny[e] = gy / mag;
+            sh.sg[e] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
+        }
+    };
+
+    // collision of the wave's row from the registers
+    auto collide_row = [&](auto intc, int y) {
+        constexpr bool INT = decltype(intc)::value;
+        const int x = x0 - 1 + lane, yy = y + wv;
+        if (lane < 1 || lane > kStripW || x >= c.nx || yy >= y1) return;
+        const int rm2 = ((yy - 1) & M) * W2, r02 = (yy & M) * W2, rp2 = ((yy + 1) & M) * W2;
+        const int rm1 = ((yy - 1) & M) * W1, r01 = (yy & M) * W1, rp1 = ((yy + 1) & M) * W1;
+        const int c2 = lane + 1, c1 = lane;
+        R gx, gy;
+        grad_ring<R, REFS>(sh.phd, sh.phb, rm2, r02, rp2, c2, gx, gy);
+        const R phb = REFS ? sh.phb[r02 + c2] : R(0);
+        const R phd = sh.phd[r02 + c2];
+        const R phi = phb + phd;
+        // 1 - phi from the reference / deviation pair (phi ~ 1 inside a bubble)
+        const R omphi = (R(1) - phb) - phd;
+        const R nxv = sh.nx[r01 + c1], nyv = sh.ny[r01 + c1];
+        // curvature: isotropic divergence of the normal field
+        const R* NX = sh.nx;
+        const R* NY = sh.ny;
+        const R kap = (R(4) * (NX[r01 + c1 + 1] - NX[r01 + c1 - 1] + NY[rp1 + c1] - NY[rm1 + c1]) +
+                       (NX[rp1 + c1 + 1] - NX[rp1 + c1 - 1] + NX[rm1 + c1 + 1] - NX[rm1 + c1 - 1]) +
+                       (NY[rp1 + c1 + 1] - NY[rm1 + c1 + 1] + NY[rp1 + c1 - 1] - NY[rm1 + c1 - 1])) *
+                      R(1.0 / 12.0);
+        double dsxd, dsyd;
+        grad_ring<R, false, double>(sh.sg, nullptr, rm1, r01, rp1, c1, dsxd, dsyd);
+        const R dsx = R(dsxd), dsy = R(dsyd);
+        R dpx, dpy;
+        grad_ring<R, false, R>(sh.ps, nullptr, rm1, r01, rp1, c1, dpx, dpy);
+        const R sig = R(sh.sg[r01 + c1]);
+        const R pstar = sh.ps[r01 + c1];
+
+        // CSF surface force: 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
+        const R ds = R(1.5) * c.W * (gx * gx + gy * gy);
+        const R nds = nxv * dsx + nyv * dsy;
+        const R Fsx = ds * (-sig * kap * nxv + dsx - nxv * nds);
+        const R Fsy = ds * (-sig * kap * nyv + dsy - nyv * nds);
+        // properties linear in phi
+        const R rho = c.rhoA + phi * c.drho;
+        const R mu = c.muA + phi * c.dmu;
+        const R omnu = R(1) / (mu / rho * inv_cs2 + R(0.5));
+        const R alpha = c.alphaA + phi * c.dalpha;
+        const R omT = R(1) / (alpha * inv_cs2 + R(0.5));
+        // pressure force -grad(p* - rho cs2), total force
+        const R Fpx = -dpx + cs2 * c.drho * gx;
+        const R Fpy = -dpy + cs2 * c.drho * gy;
+        const R Ftx = Fsx + c.Fx;
+        const R Fty = Fsy + c.Fy - (rho - c.rhoA) * c.grav;
+
+        const R bh = REFS ? c.Tlaw(R(x)) : R(0);
+        const R bq = ref_q(x, yy);
+        // live nodes are lattice nodes: x, yy need no wrap
+        if (!REG) pull9<SET_G, INT, REFS, S>(c, src, x, yy, x, yy, R(0), no_ref, G);
+        // g: momentum, velocity and pressure
+        const R jx = G[1] - G[3] + G[5] - G[6] - G[7] + G[8];
+        const R jy = G[2] - G[4] + G[5] + G[6] - G[7] - G[8];
+        const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
+        const R uy = (jy + R(0.5) * cs2 * Fty) / (rho * cs2);
+        const R p = pstar + R(0.5) * (Fpx * ux + Fpy * uy);
+        const R dV = dV_lam(c, phi, omphi);
+
+        const uint32_t o = (uint32_t)(yy * c.pitch + x) * (uint32_t)sizeof(S);
+        collide_g(G, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        store9<SET_G, S>(c, dst, o, G);
+        // f: first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
+        // the new storage reference is the FP16-rounded phi of this node
+        if (!REG) pull9<SET_F, INT, REFS, S>(c, src, x, yy, x, yy, phb, ref_f, F);
+        const R mt = c.Mphi * R(4) * phi * omphi / c.W;
+        const R nbf = REFS ? R(__half2float(__float2half_rn((float)phi))) : R(0);
+        collide_ad(F, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
+        store9<SET_F, S>(c, dst, o, F);
+        // h: temperature
+        if (!REG) pull9<SET_H, INT, REFS, S>(c, src, x, yy, x, yy, bh, no_ref, H);
+        collide_ad(H, bh, bh, R(0), R(0), omT, ux, uy);
+        store9<SET_H, S>(c, dst, o, H);
+        // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
+        if (!REG) pull9<SET_Q, INT, REFS, S>(c, src, x, yy, x, yy, bq, ref_q, Q);
+        const R psi = bq + sum9(Q);
+        const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
+        const R nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
+        collide_ad(Q, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
+        store9<SET_Q, S>(c, dst, o, Q);
+        if (REFS) {
+            const uint32_t oh = (uint32_t)(yy * c.pitch + x) * 2u;
+            Mem<__half>::st(__float2half_rn((float)nbf), rdst, oh, 0);
+            Mem<__half>::st(__float2half_rn((float)nbq), rdst, oh, rplane_b);
+        }
+    };
+
+    const bool walls = c.wallx || c.wally;
+    // prologue: references of rows y0-3 .. y0+BY+2, fields of the rows below y0
+    load_refs(y0 - 3, y0 + BY + 2);
+    __syncthreads();
+    const bool intp = xint && y0 >= 3 && y0 + 2 < c.ny;
+    if (intp) prologue(BoolC<true>{});
+    else prologue(BoolC<false>{});
+    __syncthreads();
+    if (!intp && walls) {
+        ghost_fill(y0 - 2, y0 + 1, y0 - 1, y0);
+        __syncthreads();
+    }
+    normals(y0 - 1, y0);
+    for (int y = y0; y < y1; y += BY) {
+        // lane-derived indices are recomputed per iteration rather than kept
+        // live across the loop (hoisting them costs more registers than it saves)
+        asm volatile("" : "+v"(tid), "+v"(lane), "+v"(wv));
+        const bool it = xint && y >= 3 && y + BY + 2 < c.ny;
+        if (it) {
+            if (REG) {
+                own_pulls(BoolC<true>{}, y);
+                halo_pulls(BoolC<true>{}, y);
+            } else {
+                moment_rows(BoolC<true>{}, y);
+            }
+        } else {
+            if (REG) {
+                own_pulls(BoolC<false>{}, y);
+                halo_pulls(BoolC<false>{}, y);
+            } else {
+                moment_rows(BoolC<false>{}, y);
+            }
+        }
+        __syncthreads();
+        if (!it && walls) {
+            ghost_fill(y + 2, y + BY + 1, y + 1, y + BY);
+            __syncthreads();
+        }
+        const bool more = y + BY < y1;
+        R ra0, rb0, ra1, rb1;
+        if (more) {
+            ref_fetch(y + BY + 3, tid, ra0, rb0);
+            ref_fetch(y + BY + 3, tid + NT, ra1, rb1);
+        }
+        normals(y + 1, y + BY);
+        if (more) {
+            ref_put(y + BY + 3, tid, ra0, rb0);
+            ref_put(y + BY + 3, tid + NT, ra1, rb1);
+        }
+        __syncthreads();
+        if (REG || !it) collide_row(BoolC<false>{}, y);
+        else collide_row(BoolC<true>{}, y);
     }
 }
 

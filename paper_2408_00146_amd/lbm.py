@@ -101,6 +101,7 @@ def lib():
         L.lbm_autotune.argtypes = [vp, i32]
         L.lbm_tile_count.argtypes = []
         L.lbm_tile_shape.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
+        L.lbm_tile_kind.argtypes = [i32]
         L.lbm_set_tile.argtypes = [vp, i32]
         L.lbm_get_tile.argtypes = [vp]
         L.lbm_set_graph.argtypes = [vp, i32]
@@ -126,6 +127,11 @@ def tile_shapes() -> list[tuple[int, int]]:
         _check(lib().lbm_tile_shape(i, C.byref(bx), C.byref(by)))
         out.append((bx.value, by.value))
     return out
+
+
+def tile_kinds() -> list[str]:
+    """'tile' or 'strip' for every step configuration index."""
+    return ["strip" if lib().lbm_tile_kind(i) == 1 else "tile" for i in range(lib().lbm_tile_count())]
 
 
 def workspace_bytes(cases: list[dict]) -> int:

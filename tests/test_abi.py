@@ -67,9 +67,16 @@ def test_workspace_bytes_host_only(L):
 
 
 def test_tile_table(L):
-    shapes = lbm.tile_shapes()
-    assert (64, 16) in shapes and all(bx * by >= 256 for bx, by in shapes)
+    shapes, kinds = lbm.tile_shapes(), lbm.tile_kinds()
+    assert len(shapes) == len(kinds) == L.lbm_tile_count()
+    tiles = [s for s, k in zip(shapes, kinds) if k == "tile"]
+    strips = [s for s, k in zip(shapes, kinds) if k == "strip"]
+    assert (64, 16) in tiles and all(bx * by >= 256 for bx, by in tiles)
+    # strips: 62 columns, segments a multiple of the 4 rows marched per iteration
+    assert strips and all(bx == 62 and by % 4 == 0 for bx, by in strips)
+    assert kinds[0] == "tile"
     assert L.lbm_tile_shape(99, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_tile_kind(99) == lbm.LBM_E_INVAL
 
 
 def _init_status(L, params, ws=1 << 20):

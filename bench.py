@@ -36,6 +36,8 @@ def workload(name: str):
 
     if name == "fp32_1024x512x4":
         return cases.config_fp32_runs()
+    if name == "fp32_1024x512":
+        return cases.config_fp32_runs()[3:]
     if name == "fp64_128x64":
         return [cases.config_small_fp64()]
     if name.startswith(("fp16s_", "fp32_", "fp64_")) and name.endswith("2048x1024"):
@@ -65,10 +67,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, shape) -> int | None:
+def measured_traffic(workload: str, config: str) -> int | None:
     """HBM bytes per step launch from the committed counter summary of this
-    workload and tile, or None when there is none or the kernel sources have
-    changed since the counters were taken."""
+    workload and kernel configuration ("tile 64x8", "strip 62x16"), or None
+    when there is none or the kernel sources have changed since the counters
+    were taken."""
     path = os.path.join(ROOT, "profiles", f"k_step_{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -78,7 +81,7 @@ def measured_traffic(workload: str, shape) -> int | None:
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 kv[k.strip()] = v.strip().strip("`")
-    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("tile") != f"{shape[0]}x{shape[1]}":
+    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("config") != config:
         return None
     try:
         return int(kv["traffic_bytes_per_launch"])
@@ -104,6 +107,40 @@ def cpu_baseline(params: dict, budget_s: float = 15.0) -> dict:
                       f"initial state, FP64, {dt:.1f} s"}
 
 
+COMPARE = ("fp32_1024x512", "fp16s_2048x1024", "fp32_2048x1024", "fp64_2048x1024", "batched64",
+           "large_plus_small")
+
+
+def measure(name: str, steps: int, warmup: int) -> dict:
+    """MLUPS and roofline fraction of one workload (autotuned configuration,
+    graph launches for the rate, HIP events for the step-kernel duration)."""
+    import torch
+
+    from paper_2408_00146_amd import lbm
+
+    ps = workload(name)
+    cells = sum(p["nx"] * p["ny"] for p in ps)
+    alg = sum(p["nx"] * p["ny"] * BYTES_PER_NODE[p["precision"]] for p in ps)
+    s = lbm.Solver(ps)
+    s.autotune(5)
+    s.step(warmup)
+    s.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.synchronize()
+    dt = time.perf_counter() - t0
+    s.set_kernel_timing(True)
+    s.step(min(steps, 100))
+    kms, _ = s.kernel_time_ms()
+    shape = lbm.tile_shapes()[s.tile]
+    kind = lbm.tile_kinds()[s.tile]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return {"workload": name, "cases": len(ps), "nodes": cells, "MLUPS": round(cells * steps / dt / 1e6, 1),
+            "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "config": f"{kind} {shape[0]}x{shape[1]}"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +150,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison workloads (plain FP32 single channel, FP16 storage, batched)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -149,6 +188,7 @@ def main():
     dt = time.perf_counter() - t0
     kms, nlaunch = s.kernel_time_ms()
     s.set_kernel_timing(False)
+    kind = lbm.tile_kinds()[s.tile]
     for i in range(min(len(ps), 4)):
         d = s.reduce(i)
         log(f"case {i}: step {d['step']} xc {d['xc']:.3f} ux {d['ux']:.3e} nonfinite {d['nonfinite']}")
@@ -170,13 +210,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cases": len(ps), "nodes": cells,
                    "grids": sorted({f"{p['nx']}x{p['ny']}" for p in ps}),
-                   "tile": list(shape), "parallelism": "single GPU"},
+                   "kernel_config": f"{kind} {shape[0]}x{shape[1]}", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, shape),
-                     "kernel": "k_step", "avg_launch_ms": round(kms, 5), "launches": nlaunch,
+                     "traffic": measured_traffic(args.workload, f"{kind} {shape[0]}x{shape[1]}"),
+                     "kernel": "k_strip" if kind == "strip" else "k_step", "avg_launch_ms": round(kms, 5),
+                     "launches": nlaunch,
                      "alg_bytes_per_launch": alg_bytes},
     }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_compare:
+        # the metric compares batching and FP16 storage against the plain FP32 path
+        line["compare"] = []
+        for name in COMPARE:
+            line["compare"].append(measure(name, 300, 30))
+            log(f"compare {line['compare'][-1]}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ps[0])
     print(json.dumps(line), flush=True)

@@ -43,10 +43,13 @@ typedef enum {
 } lbm_status;
 
 /* Population storage per case.  Collision arithmetic is FP64 for LBM_FP64 and
- * FP32 otherwise.  LBM_FP32 and LBM_FP16S store deviations from the rest
- * equilibrium, X_a - w_a X_ref(x), scaled by 1 (FP32) or 2^10 (FP16), with
- * X_ref = 0 for f and g, the linear wall-temperature law for h, and psi_bulk
- * for q.  LBM_FP64 stores the populations themselves. */
+ * FP32 otherwise (sigma and its gradient are always FP64).  LBM_FP32 and
+ * LBM_FP16S store deviations from the rest equilibrium of a per-node
+ * reference, X_a - w_a X_ref(x), scaled by 1 (FP32) or 2^10 (FP16): X_ref is
+ * the FP16-rounded phi, p* and psi of the node that wrote the value for f, g
+ * and q (kept in three FP16 planes next to each population buffer), and the
+ * linear wall-temperature law for h.  LBM_FP64 stores the populations
+ * themselves.  Every entry point exchanges full FP64 values. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
 
 /* Surface tension equation of state (Sec. 2.1). */

@@ -74,7 +74,8 @@ __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
 
 template <int ST, int BX, int BY>
-__global__ __launch_bounds__(256) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
+// Three workgroups per CU (<= 168 VGPRs) for the FP32/FP16 kernels; FP64 keeps two.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 2 : 3))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
                                               int ntiles, const int64_t* __restrict__ steps, int t)
 {
     using R = typename std::conditional<ST == ST_F64, double, float>::type;
@@ -273,8 +274,8 @@ __device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, 
 // back by y itself through the wall rule of direction abar, so its value is
 // the inverse of that bounce-back / anti-bounce-back.  Reduced-precision
 // storage is relative to the slot node's own references: the FP16-rounded
-// phi and psi of the state at y (written to the reference planes), and the
-// linear wall law for h.
+// phi, psi and p* of the state at y (written to the reference planes), and
+// the linear wall law for h.
 template <typename S, typename R>
 __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x, int y0y)
 {
@@ -283,16 +284,19 @@ __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x,
     const R sc = R(cd.scale);
     double ref[4] = {0.0, 0.0, 0.0, 0.0};
     if (cd.refs) {
-        double sf = 0.0, sq = 0.0;
+        double sf = 0.0, sq = 0.0, sg = 0.0;
         for (int a = 0; a < 9; ++a) {
             sf += src_pop(cd, s, SET_F, a, y0x, y0y);
             sq += src_pop(cd, s, SET_Q, a, y0x, y0y);
+            sg += src_pop(cd, s, SET_G, a, y0x, y0y);
         }
-        const __half hf = __float2half_rn((float)sf), hq = __float2half_rn((float)sq);
+        const __half hf = __float2half_rn((float)sf), hq = __float2half_rn((float)sq), hg = __float2half_rn((float)sg);
         cd.rbuf[b][o] = hf;
         cd.rbuf[b][cd.plane + o] = hq;
+        cd.rbuf[b][2 * cd.plane + o] = hg;
         ref[SET_F] = (double)__half2float(hf);
         ref[SET_Q] = (double)__half2float(hq);
+        ref[SET_G] = (double)__half2float(hg);
         ref[SET_H] = cd.T0 + cd.gradT * ((double)y0x - cd.xT0);
     }
     for (int set = 0; set < 4; ++set) {
@@ -365,9 +369,10 @@ __device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
     };
     auto rf = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[node(ux, uy)])) : R(0); };
     auto rq = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[c.plane + node(ux, uy)])) : R(0); };
+    auto rp = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[2 * (int64_t)c.plane + node(ux, uy)])) : R(0); };
     auto none = [&](int, int) -> R { return R(0); };
     export_set<SET_F, S>(c, src, x, y, out, n, rf(x, y), rf);
-    export_set<SET_G, S>(c, src, x, y, out, n, R(0), none);
+    export_set<SET_G, S>(c, src, x, y, out, n, rp(x, y), rp);
     export_set<SET_H, S>(c, src, x, y, out, n, REFS ? c.Tlaw(R(x)) : R(0), none);
     export_set<SET_Q, S>(c, src, x, y, out, n, rq(x, y), rq);
 }
@@ -414,8 +419,8 @@ int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * pitch_of(c.nx) * c.ny * elem_bytes(c.precision)); }
 
-// Per-node storage references (phi, psi) of reduced-precision cases: 2 FP16 planes per buffer.
-size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)2 * pitch_of(c.nx) * c.ny * 2); }
+// Per-node storage references (phi, psi, p*) of reduced-precision cases: 3 FP16 planes per buffer.
+size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)3 * pitch_of(c.nx) * c.ny * 2); }
 
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
 

@@ -17,9 +17,9 @@
 // consecutive x reads/writes contiguous memory.
 //
 // Reduced-precision storage (FP32, FP16 x 2^10) keeps each population as a
-// deviation from the rest equilibrium of a per-node reference: for f and q
-// the FP16-rounded phi and psi of the node that wrote it (two extra FP16
-// planes per buffer), for h the linear wall-temperature law, for g zero.
+// deviation from the rest equilibrium of a per-node reference: for f, q and g
+// the FP16-rounded phi, psi and p* of the node that wrote it (three extra
+// FP16 planes per buffer), for h the linear wall-temperature law.
 // Deviations are O(u, grad) small, so FP16/FP32 keep their relative
 // precision on them; phi and psi are carried as reference + deviation until
 // they enter a difference, so gradients stay accurate where phi is ~1.
@@ -59,7 +59,7 @@ struct CaseDev {
     uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
     uint32_t ref_bytes; // bytes of one reference buffer (2 FP16 planes)
     void* buf[2];       // ping-pong population buffers
-    __half* rbuf[2];    // per-node references [2 = phi, psi][ny][pitch] of each buffer (refs only)
+    __half* rbuf[2];    // per-node references [3 = phi, psi, p*][ny][pitch] of each buffer (refs only)
 };
 
 struct TileRec {
@@ -195,7 +195,7 @@ __device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int
 {
     constexpr int EX = ex(A), EY = ey(A);
     constexpr uint32_t E = sizeof(S);
-    constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q);
+    constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q || SET == SET_G);
     const R w = R(wt(A));
     if (INT) {
         // shift of the source folded into the scalar offset (never negative: plane >= pitch + 1)
@@ -406,6 +406,61 @@ __device__ __forceinline__ void collide_g(R g[9], R pstar, R jx, R jy, R p, R rh
     raw_to_pop(m, g);
 }
 
+// The same collision with g held as deviations from w_a b (b = the node's
+// storage reference of p*, FP16-exact) and returned as deviations from
+// w_a nb (nb = the new reference).  The moments of w_a X are X (1, 0, 0,
+// 1/3, 1/3, 0, 0, 0, 1/9); subtracting nb times them before P^-1 leaves every
+// large term out of the stored values.  pd = p - nb is formed by the caller
+// from (b - nb) + sum(dev) + F_p.u / 2 without cancellation.
+template <typename R>
+__device__ __forceinline__ void collide_g_dev(R g[9], R pstar, R jx, R jy, R pd, R nb, R rho, R ux, R uy, R Ftx,
+                                              R Fty, R Fpx, R Fpy, R om)
+{
+    const R cs2 = R(1.0 / 3.0);
+    const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    // deviatoric and shear pre-collision central moments: the reference part
+    // of the raw moments (b/3 in both 20 and 02, 0 in 11) cancels
+    const R d20 = g[1] + g[3] + g[5] + g[6] + g[7] + g[8];
+    const R d02 = g[2] + g[4] + g[5] + g[6] + g[7] + g[8];
+    const R r11 = g[5] - g[6] + g[7] - g[8];
+    const R e2d = (d20 - d02) - R(2) * (ux * jx - uy * jy) + (uxx - uyy) * pstar;
+    const R e11 = r11 - uy * jx - ux * jy + uxy * pstar;
+    // equilibria; primed ones have nb times the rest moments removed
+    const R vp = (nb + pd) - rho * cs2;
+    const R q00p = pd, q10 = -vp * ux, q01 = -vp * uy;
+    const R q20p = pd * cs2 + vp * uxx, q02p = pd * cs2 + vp * uyy, q11 = vp * uxy;
+    const R q21 = -vp * (uxx + cs2) * uy, q12 = -vp * (uyy + cs2) * ux;
+    const R q22p = pd * cs2 * cs2 + vp * (cs2 * (uxx + uyy) + uxx * uyy);
+    // source moments, Gamma00 = Fp . u
+    const R G = Fpx * ux + Fpy * uy;
+    const R s10 = cs2 * Ftx - ux * G, s01 = cs2 * Fty - uy * G;
+    const R s20 = R(2) * cs2 * Fpx * ux + (uxx + cs2) * G;
+    const R s02 = R(2) * cs2 * Fpy * uy + (uyy + cs2) * G;
+    const R s11 = cs2 * (Fpx * uy + Fpy * ux) + uxy * G;
+    const R h = R(0.5);
+    const R t00p = q00p + h * G;
+    const R t10 = q10 + h * s10;
+    const R t01 = q01 + h * s01;
+    const R t2sp = (q20p + q02p) + h * (s20 + s02);
+    const R t2d = e2d + om * ((q20p - q02p) - e2d) + (R(1) - h * om) * (s20 - s02);
+    const R t11 = e11 + om * (q11 - e11) + (R(1) - h * om) * s11;
+    const R t20p = h * (t2sp + t2d), t02p = h * (t2sp - t2d);
+    // full values where they only multiply powers of u
+    const R T00 = t00p + nb, T20 = t20p + nb * cs2, T02 = t02p + nb * cs2;
+    R m[9];
+    m[0] = t00p;
+    m[1] = ux * T00 + t10;
+    m[2] = uy * T00 + t01;
+    m[3] = uxx * T00 + R(2) * ux * t10 + t20p;
+    m[4] = uyy * T00 + R(2) * uy * t01 + t02p;
+    m[5] = uxy * T00 + uy * t10 + ux * t01 + t11;
+    m[6] = uxx * uy * T00 + R(2) * uxy * t10 + uxx * t01 + uy * T20 + R(2) * ux * t11 + q21;
+    m[7] = ux * uyy * T00 + uyy * t10 + R(2) * uxy * t01 + ux * T02 + R(2) * uy * t11 + q12;
+    m[8] = uxx * uyy * T00 + R(2) * ux * uyy * t10 + R(2) * uxx * uy * t01 + uyy * T20 + uxx * T02 +
+           R(4) * uxy * t11 + R(2) * uy * q21 + R(2) * ux * q12 + q22p;
+    raw_to_pop(m, g);
+}
+
 // ------------------------------------------------------------ tile body
 enum { MODE_STEP = 0, MODE_MACRO = 1 };
 
@@ -425,12 +480,15 @@ struct Smem {
     static constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     static constexpr int N3 = REFS ? W3 * H3 : 1;
     static constexpr int N2B = REFS ? W2 * H2 : 1;
+    static constexpr int N1B = REFS ? W1 * H1 : 1;
     R rf[N3];   // phi reference
     R rq[N3];   // psi reference
+    R rp[N3];   // p* reference
     R phd[W2 * H2];
     R phb[N2B];
     double sg[W1 * H1];  // sigma (FP64)
-    R ps[W1 * H1];
+    R ps[W1 * H1];   // p* (deviation from its reference with reduced-precision storage)
+    R psb[N1B];      // p* reference
     R ts[W1 * H1];   // T - T_w(x): deviation from the linear wall law at the slot's column
     R pq[W1 * H1];   // psi
     R nx[W1 * H1];
@@ -468,6 +526,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     // per-node references of the f and q sets at unwrapped tile coordinates
     auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
     auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
+    auto ref_p = [&](int ux, int uy) -> R { return REFS ? sh.rp[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
     auto no_ref = [&](int, int) -> R { return R(0); };
     // lattice node of an unwrapped coordinate on a periodic axis
     auto wrapx = [&](int u) { return INT || c.wallx ? u : (u < 0 ? u + c.nx : (u >= c.nx ? u - c.nx : u)); };
@@ -480,7 +539,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     if (REFS) {
         for (int k = tid; k < W3 * H3; k += NT) {
             const int ux = x0 - 3 + k % W3, uy = y0 - 3 + k / W3;
-            R a = R(0), b = R(0);
+            R a = R(0), b = R(0), d = R(0);
             if (!ghostx(ux) && !ghosty(uy)) {
                 int mx = wrapx(ux), my = wrapy(uy);
                 // beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
@@ -488,10 +547,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                     const uint32_t ob = (uint32_t)(my * c.pitch + mx) * 2u;
                     a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
                     b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
+                    d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
                 }
             }
             sh.rf[k] = a;
             sh.rq[k] = b;
+            sh.rp[k] = d;
         }
         __syncthreads();
     }
@@ -513,8 +574,10 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         sh.phd[k] = sum9(v);
         if (REFS) sh.phb[k] = bf;
         if (in1) {
-            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, R(0), no_ref, v);
+            const R bp = ref_p(ux, uy);
+            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, v);
             sh.ps[e1] = sum9(v);
+            if (REFS) sh.psb[e1] = bp;
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, v);
             // T - T_w(ux): with the linear-law reference exactly gradT (mx - ux) + sum
@@ -556,6 +619,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             if (in1 && mlx >= 1 && mlx <= BX + 2 && mly >= 1 && mly <= BY + 2) {
                 const int e1 = (ly - 1) * W1 + (lx - 1), m1 = (mly - 1) * W1 + (mlx - 1);
                 sh.ps[e1] = sh.ps[m1];
+                if (REFS) sh.psb[e1] = sh.psb[m1];
                 double T = c.Tlaw_d((double)mux) + (double)sh.ts[m1];
                 R q = sh.pq[m1];
                 if (ys >= 0 && c.t_dir(ys)) T = 2.0 * c.Tlaw_d((double)mx) - T;
@@ -612,9 +676,10 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         grad2<R, false, double>(sh.sg, nullptr, p1, W1, dsxd, dsyd);
         const R dsx = R(dsxd), dsy = R(dsyd);
         R dpx, dpy;
-        grad2<R, false, R>(sh.ps, nullptr, p1, W1, dpx, dpy);
+        grad2<R, REFS, R>(sh.ps, sh.psb, p1, W1, dpx, dpy);
         const R sig = R(sh.sg[p1]);
-        const R pstar = sh.ps[p1];
+        const R pbase = REFS ? sh.psb[p1] : R(0);
+        const R pstar = pbase + sh.ps[p1];
 
         // CSF surface force: 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
         const R ds = R(1.5) * c.W * (gx * gx + gy * gy);
@@ -637,7 +702,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
 
         // g: momentum, velocity and pressure
         R g[9];
-        pull9<SET_G, INT, REFS, S>(c, src, x, y, x, y, R(0), no_ref, g);
+        pull9<SET_G, INT, REFS, S>(c, src, x, y, x, y, pbase, ref_p, g);
         const R jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
         const R jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
         const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
@@ -688,7 +753,14 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         }
 
         const uint32_t o = (uint32_t)(y * c.pitch + x);
-        collide_g(g, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        // the new p* reference is the FP16-rounded p* of this node
+        const R nbp = REFS ? R(__half2float(__float2half_rn((float)pstar))) : R(0);
+        if (REFS) {
+            const R pd = (pbase - nbp) + sh.ps[p1] + R(0.5) * (Fpx * ux + Fpy * uy);
+            collide_g_dev(g, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        } else {
+            collide_g(g, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        }
         store9<SET_G, S>(c, dst, o * (uint32_t)sizeof(S), g);
 
         // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
@@ -717,6 +789,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         if (REFS) {
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
             Mem<__half>::st(__float2half_rn((float)nbq), rdst, o * 2u, rplane_b);
+            Mem<__half>::st(__float2half_rn((float)nbp), rdst, o * 2u, 2u * rplane_b);
         }
     }
 }
@@ -753,10 +826,12 @@ struct StripSmem {
     static constexpr int W3 = kStripW + 6, W2 = kStripW + 4, W1 = kStripW + 2;
     R rf[REFS ? RING * W3 : 1];  // phi reference
     R rq[REFS ? RING * W3 : 1];  // psi reference
+    R rp[REFS ? RING * W3 : 1];  // p* reference
     R phd[RING * W2];            // phi deviation from its reference
     R phb[REFS ? RING * W2 : 1];
     double sg[RING * W1];        // sigma (FP64)
-    R ps[RING * W1];             // p*
+    R ps[RING * W1];             // p* (deviation from its reference with reduced-precision storage)
+    R psb[REFS ? RING * W1 : 1]; // p* reference
     R ts[RING * W1];             // T - T_w(column)
     R pq[RING * W1];             // psi
     R nx[RING * W1];
@@ -805,6 +880,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
     auto i1 = [&](int ux, int uy) { return (uy & M) * W1 + (ux - x0 + 1); };
     auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[i3(ux, uy)] : R(0); };
     auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[i3(ux, uy)] : R(0); };
+    auto ref_p = [&](int ux, int uy) -> R { return REFS ? sh.rp[i3(ux, uy)] : R(0); };
     auto no_ref = [&](int, int) -> R { return R(0); };
     // lattice node of an unwrapped coordinate (overhangs are shorter than the lattice)
     auto wrapx = [&](int v) { return c.wallx ? v : (v < 0 ? v + c.nx : (v >= c.nx ? v - c.nx : v)); };
@@ -820,37 +896,42 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const int n = (rb - ra + 1) * W3;
         for (int k = tid; k < n; k += NT) {
             const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
-            R a = R(0), b = R(0);
+            R a = R(0), b = R(0), d = R(0);
             if (!ghostx(ux) && !ghosty(uy)) {
                 const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
                 a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
                 b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
+                d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
             }
             const int e = i3(ux, uy);
             sh.rf[e] = a;
             sh.rq[e] = b;
+            sh.rp[e] = d;
         }
     };
 
     // the same for the next iteration's rows, split into issue and commit so
     // that the loads are in flight during the normals (at most 2 slots per thread)
     static_assert(BY * W3 <= 2 * NT, "reference prefetch holds two slots per thread");
-    auto ref_fetch = [&](int ra, int k, R& a, R& b) {
+    auto ref_fetch = [&](int ra, int k, R& a, R& b, R& d) {
         a = R(0);
         b = R(0);
+        d = R(0);
         if (!REFS || k >= BY * W3) return;
         const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
         if (!ghostx(ux) && !ghosty(uy)) {
             const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
             a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
             b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
+            d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
         }
     };
-    auto ref_put = [&](int ra, int k, R a, R b) {
+    auto ref_put = [&](int ra, int k, R a, R b, R d) {
         if (!REFS || k >= BY * W3) return;
         const int e = i3(x0 - 3 + k % W3, ra + k / W3);
         sh.rf[e] = a;
         sh.rq[e] = b;
+        sh.rp[e] = d;
     };
 
     // p*, T, psi of the node at unwrapped (ux, uy) into the rings (ghosts: zeros)
@@ -860,8 +941,9 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
         R v[9];
         R pv = R(0), tv = R(0), qv = R(0);
+        const R bp = ref_p(ux, uy);
         if (!gh) {
-            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, R(0), no_ref, v);
+            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, v);
             pv = sum9(v);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, v);
@@ -872,6 +954,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         }
         const int e = i1(ux, uy);
         sh.ps[e] = pv;
+        if (REFS) sh.psb[e] = gh ? R(0) : bp;
         sh.ts[e] = tv;
         sh.pq[e] = qv;
     };
@@ -902,11 +985,11 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const int ux = x0 - 1 + lane, uy = y + wv;
         const bool gh = !INT && (ghostx(ux) || ghosty(uy));
         const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
-        const R bf = ref_f(ux, uy), bq = ref_q(ux, uy);
+        const R bf = ref_f(ux, uy), bq = ref_q(ux, uy), bp = ref_p(ux, uy);
         const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
         if (!gh) {
             pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, F);
-            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, R(0), no_ref, G);
+            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, G);
             pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, H);
             pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
         } else {
@@ -921,6 +1004,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         if (wv >= 1) {
             const int e = i1(ux, uy);
             sh.ps[e] = gh ? R(0) : sum9(G);
+            if (REFS) sh.psb[e] = gh ? R(0) : bp;
             sh.ts[e] = gh ? R(0) : (REFS ? c.gradT * R(mx - ux) + sum9(H) : R((double)sum9(H) - c.Tlaw_d((double)ux)));
             sh.pq[e] = gh ? R(0) : bq + sum9(Q);
         }
@@ -1002,6 +1086,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             if (uy >= ea && uy <= eb && col >= 1 && col <= W1 && mc >= 0 && mc < W1) {
                 const int e = i1(ux, uy), m = i1(mux, muy);
                 sh.ps[e] = sh.ps[m];
+                if (REFS) sh.psb[e] = sh.psb[m];
                 double T = c.Tlaw_d((double)mux) + (double)sh.ts[m];
                 R q = sh.pq[m];
                 if (ys >= 0 && c.t_dir(ys)) T = 2.0 * c.Tlaw_d((double)mx) - T;
@@ -1056,9 +1141,10 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         grad_ring<R, false, double>(sh.sg, nullptr, rm1, r01, rp1, c1, dsxd, dsyd);
         const R dsx = R(dsxd), dsy = R(dsyd);
         R dpx, dpy;
-        grad_ring<R, false, R>(sh.ps, nullptr, rm1, r01, rp1, c1, dpx, dpy);
+        grad_ring<R, REFS, R>(sh.ps, sh.psb, rm1, r01, rp1, c1, dpx, dpy);
         const R sig = R(sh.sg[r01 + c1]);
-        const R pstar = sh.ps[r01 + c1];
+        const R pbase = REFS ? sh.psb[r01 + c1] : R(0);
+        const R pstar = pbase + sh.ps[r01 + c1];
 
         // CSF surface force: 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
         const R ds = R(1.5) * c.W * (gx * gx + gy * gy);
@@ -1080,7 +1166,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const R bh = REFS ? c.Tlaw(R(x)) : R(0);
         const R bq = ref_q(x, yy);
         // live nodes are lattice nodes: x, yy need no wrap
-        if (!REG) pull9<SET_G, INT, REFS, S>(c, src, x, yy, x, yy, R(0), no_ref, G);
+        if (!REG) pull9<SET_G, INT, REFS, S>(c, src, x, yy, x, yy, pbase, ref_p, G);
         // g: momentum, velocity and pressure
         const R jx = G[1] - G[3] + G[5] - G[6] - G[7] + G[8];
         const R jy = G[2] - G[4] + G[5] + G[6] - G[7] - G[8];
@@ -1090,7 +1176,14 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const R dV = dV_lam(c, phi, omphi);
 
         const uint32_t o = (uint32_t)(yy * c.pitch + x) * (uint32_t)sizeof(S);
-        collide_g(G, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        // the new p* reference is the FP16-rounded p* of this node
+        const R nbp = REFS ? R(__half2float(__float2half_rn((float)pstar))) : R(0);
+        if (REFS) {
+            const R pd = (pbase - nbp) + sh.ps[r01 + c1] + R(0.5) * (Fpx * ux + Fpy * uy);
+            collide_g_dev(G, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        } else {
+            collide_g(G, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+        }
         store9<SET_G, S>(c, dst, o, G);
         // f: first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
         // the new storage reference is the FP16-rounded phi of this node
@@ -1114,6 +1207,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             const uint32_t oh = (uint32_t)(yy * c.pitch + x) * 2u;
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, oh, 0);
             Mem<__half>::st(__float2half_rn((float)nbq), rdst, oh, rplane_b);
+            Mem<__half>::st(__float2half_rn((float)nbp), rdst, oh, 2u * rplane_b);
         }
     };
 
@@ -1156,15 +1250,15 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             __syncthreads();
         }
         const bool more = y + BY < y1;
-        R ra0, rb0, ra1, rb1;
+        R ra0, rb0, rd0, ra1, rb1, rd1;
         if (more) {
-            ref_fetch(y + BY + 3, tid, ra0, rb0);
-            ref_fetch(y + BY + 3, tid + NT, ra1, rb1);
+            ref_fetch(y + BY + 3, tid, ra0, rb0, rd0);
+            ref_fetch(y + BY + 3, tid + NT, ra1, rb1, rd1);
         }
         normals(y + 1, y + BY);
         if (more) {
-            ref_put(y + BY + 3, tid, ra0, rb0);
-            ref_put(y + BY + 3, tid + NT, ra1, rb1);
+            ref_put(y + BY + 3, tid, ra0, rb0, rd0);
+            ref_put(y + BY + 3, tid + NT, ra1, rb1, rd1);
         }
         __syncthreads();
         if (REG || !it) collide_row(BoolC<false>{}, y);

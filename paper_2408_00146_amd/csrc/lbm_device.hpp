@@ -78,6 +78,7 @@ struct Ctx {
     R rhoA, drho, muA, dmu, alphaA, dalpha;
     R om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     R Fx, Fy, grav, scale, inv_scale;
+    R pw0, pw1, pw2, pw3;  // psi wall values as separate fields (selected without memory access)
     // surface tension and the wall-temperature law in FP64 (sigma and its
     // gradient are formed in FP64 in every precision)
     double T0d, gradTd, xT0d, s0d, sTd, sTTd, Trefd, betad, ipsid;
@@ -95,12 +96,14 @@ struct Ctx {
         om_phi = R(c.om_phi); om_psi = R(c.om_psi); Mphi = R(c.Mphi); W = R(c.W); Dpsi = R(c.Dpsi);
         s_lam = R(c.s_lam); w_lam = R(c.w_lam); Fx = R(c.Fx); Fy = R(c.Fy); grav = R(c.grav);
         scale = R(c.scale); inv_scale = R(c.inv_scale);
+        pw0 = R(c.psi_w[0]); pw1 = R(c.psi_w[1]); pw2 = R(c.psi_w[2]); pw3 = R(c.psi_w[3]);
         T0d = c.T0; gradTd = c.gradT; xT0d = c.xT0; s0d = c.s0; sTd = c.sT; sTTd = c.sTT; Trefd = c.Tref;
         betad = c.beta; ipsid = c.inv_psi_inf;
     }
     __device__ bool t_dir(int side) const { return (tbc >> side) & 1; }
     __device__ bool p_dir(int side) const { return (pbc >> side) & 1; }
     __device__ R psi_wall(int side) const { return R(psi_w[side]); }
+    __device__ R psi_wall_sel(int side) const { return side == 0 ? pw0 : (side == 1 ? pw1 : (side == 2 ? pw2 : pw3)); }
     // Imposed linear wall-temperature law.
     __device__ R Tlaw(R x) const { return T0 + gradT * (x - xT0); }
     __device__ double Tlaw_d(double x) const { return T0d + gradTd * (x - xT0d); }
@@ -206,34 +209,40 @@ __device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int
         if (REFS && SET == SET_H && EX != 0) val -= w * c.gradT * R(EX);  // linear-law reference of column mx - ex
         return val;
     }
+    // Branch-free: the source node or, beyond a wall, the node itself in the
+    // opposite direction is selected per lane, so that the nine loads of a
+    // set can be issued together.
     int sx = mx - EX, sy = my - EY;
-    bool wall = false;
-    int side = 0;
-    if (EY != 0 && (sy < 0 || sy >= c.ny)) {
-        if (c.wally) { wall = true; side = sy < 0 ? 2 : 3; }
-        else sy += sy < 0 ? c.ny : -c.ny;
-    }
-    if (EX != 0 && !wall && (sx < 0 || sx >= c.nx)) {
-        if (c.wallx) { wall = true; side = sx < 0 ? 0 : 1; }
-        else sx += sx < 0 ? c.nx : -c.nx;
-    }
-    if (!wall) {
-        R val = dec<S, R>(Mem<S>::ld(src.r, (uint32_t)(sy * c.pitch + sx) * E, (uint32_t)((SET * 9 + A) * c.plane) * E),
-                          c.inv_scale);
-        if (NODE_REF) val += w * (rf(ux - EX, uy - EY) - base);
-        if (REFS && SET == SET_H && EX != 0) val += w * c.gradT * R(sx - mx);  // linear-law reference of column sx
-        return val;
-    }
+    const bool outy = EY != 0 && (sy < 0 || sy >= c.ny);
+    const bool wy = outy && c.wally;
+    if (EY != 0) sy = (outy && !c.wally) ? sy + (sy < 0 ? c.ny : -c.ny) : sy;
+    const bool outx = EX != 0 && !wy && (sx < 0 || sx >= c.nx);
+    const bool wx = outx && c.wallx;
+    if (EX != 0) sx = (outx && !c.wallx) ? sx + (sx < 0 ? c.nx : -c.nx) : sx;
+    const bool wall = wy || wx;
+    // the wall a direction can cross is fixed by its sign: e_y > 0 pulls
+    // from below (side 2), e_x > 0 from the left (side 0)
+    constexpr int YS = EY > 0 ? 2 : 3, XS = EX > 0 ? 0 : 1;
     constexpr int B = opp(A);
-    R val = dec<S, R>(Mem<S>::ld(src.r, (uint32_t)(my * c.pitch + mx) * E, (uint32_t)((SET * 9 + B) * c.plane) * E),
-                      c.inv_scale);
-    if (NODE_REF) val += w * (rf(ux, uy) - base);
-    if (SET == SET_H && c.t_dir(side)) {
+    const uint32_t node = wall ? (uint32_t)(my * c.pitch + mx) : (uint32_t)(sy * c.pitch + sx);
+    const uint32_t pln = wall ? (uint32_t)((SET * 9 + B) * c.plane) : (uint32_t)((SET * 9 + A) * c.plane);
+    R val = dec<S, R>(Mem<S>::ld(src.r, (node + pln) * E, 0u), c.inv_scale);
+    if (NODE_REF) {
+        // beyond a wall the slot is the node's own, stored against its own reference
+        const int rx = wall ? ux : ux - EX, ry = wall ? uy : uy - EY;
+        val += w * (rf(rx, ry) - base);
+    }
+    // linear-law reference of column sx (not at a wall, where the slot is the node's own)
+    if (REFS && SET == SET_H && EX != 0) val += wall ? R(0) : w * c.gradT * R(sx - mx);
+    if (SET == SET_H) {
         // X_w - base; with the linear-law reference exactly -gradT ex / 2
         const R d = REFS ? R(-0.5) * c.gradT * R(EX) : c.Tlaw(R(mx) - R(0.5) * R(EX)) - base;
-        return -val + R(2) * w * d;
+        if ((wy && c.t_dir(YS)) || (wx && c.t_dir(XS))) val = -val + R(2) * w * d;
     }
-    if (SET == SET_Q && c.p_dir(side)) return -val + R(2) * w * (c.psi_wall(side) - base);
+    if (SET == SET_Q) {
+        if (wy && c.p_dir(YS)) val = -val + R(2) * w * (c.psi_wall_sel(YS) - base);
+        else if (wx && c.p_dir(XS)) val = -val + R(2) * w * (c.psi_wall_sel(XS) - base);
+    }
     return val;
 }
 
@@ -250,6 +259,9 @@ __device__ __forceinline__ void pull9(const Ctx<R>& c, View src, int ux, int uy,
     v[6] = pull<SET, 6, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
     v[7] = pull<SET, 7, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
     v[8] = pull<SET, 8, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    // near walls / periodic seams: keep the scheduler from hoisting the next
+    // set's loads above this one (nine loads in flight, no spills)
+    if (!INT) __builtin_amdgcn_sched_barrier(0);
 }
 
 // Store the 9 post-collision populations of a set at node offset v (bytes).

@@ -193,8 +193,36 @@ struct View {
 // beyond both a y-wall and an x-wall follows the y-wall's rule.  INT: the
 // caller guarantees every source lies inside the lattice (no wrap, no wall).
 // RF(ux, uy) returns the per-node reference of set SET at unwrapped node u.
+// Neighbourhood of a node for the general (wall / periodic-seam) pull,
+// computed once per node: the source column for e_x = +1 / -1, the source
+// row offsets for e_y = +1 / 0 / -1 (periodic wrap applied), and whether
+// that source lies beyond a wall.
+struct Nbr {
+    int sxm, sxp;        // source x for e_x = +1 (x - 1) and e_x = -1 (x + 1)
+    int rym, ry0, ryp;   // row offsets (row * pitch) of y - 1, y, y + 1
+    bool wxm, wxp, wym, wyp;
+};
+
+template <typename R>
+__device__ __forceinline__ Nbr nbr_of(const Ctx<R>& c, int mx, int my)
+{
+    Nbr n;
+    const int xl = mx - 1, xr = mx + 1, yd = my - 1, yu = my + 1;
+    n.wxm = c.wallx && xl < 0;
+    n.wxp = c.wallx && xr >= c.nx;
+    n.wym = c.wally && yd < 0;
+    n.wyp = c.wally && yu >= c.ny;
+    n.sxm = xl < 0 ? xl + c.nx : xl;
+    n.sxp = xr >= c.nx ? xr - c.nx : xr;
+    n.rym = (yd < 0 ? yd + c.ny : yd) * c.pitch;
+    n.ryp = (yu >= c.ny ? yu - c.ny : yu) * c.pitch;
+    n.ry0 = my * c.pitch;
+    return n;
+}
+
 template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
-__device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf)
+__device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf,
+                                  const Nbr& nb)
 {
     constexpr int EX = ex(A), EY = ey(A);
     constexpr uint32_t E = sizeof(S);
@@ -211,20 +239,17 @@ __device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int
     }
     // Branch-free: the source node or, beyond a wall, the node itself in the
     // opposite direction is selected per lane, so that the nine loads of a
-    // set can be issued together.
-    int sx = mx - EX, sy = my - EY;
-    const bool outy = EY != 0 && (sy < 0 || sy >= c.ny);
-    const bool wy = outy && c.wally;
-    if (EY != 0) sy = (outy && !c.wally) ? sy + (sy < 0 ? c.ny : -c.ny) : sy;
-    const bool outx = EX != 0 && !wy && (sx < 0 || sx >= c.nx);
-    const bool wx = outx && c.wallx;
-    if (EX != 0) sx = (outx && !c.wallx) ? sx + (sx < 0 ? c.nx : -c.nx) : sx;
+    // set can be issued together.  A y wall wins over an x wall (corner links);
+    // the wall a direction can cross is fixed by its sign: e_y > 0 pulls from
+    // below (side 2), e_x > 0 from the left (side 0).
+    const int sx = EX > 0 ? nb.sxm : (EX < 0 ? nb.sxp : mx);
+    const int rs = EY > 0 ? nb.rym : (EY < 0 ? nb.ryp : nb.ry0);
+    const bool wy = EY > 0 ? nb.wym : (EY < 0 ? nb.wyp : false);
+    const bool wx = !wy && (EX > 0 ? nb.wxm : (EX < 0 ? nb.wxp : false));
     const bool wall = wy || wx;
-    // the wall a direction can cross is fixed by its sign: e_y > 0 pulls
-    // from below (side 2), e_x > 0 from the left (side 0)
     constexpr int YS = EY > 0 ? 2 : 3, XS = EX > 0 ? 0 : 1;
     constexpr int B = opp(A);
-    const uint32_t node = wall ? (uint32_t)(my * c.pitch + mx) : (uint32_t)(sy * c.pitch + sx);
+    const uint32_t node = wall ? (uint32_t)(nb.ry0 + mx) : (uint32_t)(rs + sx);
     const uint32_t pln = wall ? (uint32_t)((SET * 9 + B) * c.plane) : (uint32_t)((SET * 9 + A) * c.plane);
     R val = dec<S, R>(Mem<S>::ld(src.r, (node + pln) * E, 0u), c.inv_scale);
     if (NODE_REF) {
@@ -250,15 +275,16 @@ template <int SET, bool INT, bool REFS, typename S, typename R, typename RF>
 __device__ __forceinline__ void pull9(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf,
                                       R v[9])
 {
-    v[0] = pull<SET, 0, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[1] = pull<SET, 1, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[2] = pull<SET, 2, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[3] = pull<SET, 3, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[4] = pull<SET, 4, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[5] = pull<SET, 5, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[6] = pull<SET, 6, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[7] = pull<SET, 7, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
-    v[8] = pull<SET, 8, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf);
+    const Nbr nb = INT ? Nbr{} : nbr_of(c, mx, my);
+    v[0] = pull<SET, 0, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[1] = pull<SET, 1, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[2] = pull<SET, 2, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[3] = pull<SET, 3, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[4] = pull<SET, 4, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[5] = pull<SET, 5, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[6] = pull<SET, 6, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[7] = pull<SET, 7, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
+    v[8] = pull<SET, 8, INT, REFS, S, R>(c, src, ux, uy, mx, my, base, rf, nb);
     // near walls / periodic seams: keep the scheduler from hoisting the next
     // set's loads above this one (nine loads in flight, no spills)
     if (!INT) __builtin_amdgcn_sched_barrier(0);

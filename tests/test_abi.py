@@ -86,7 +86,9 @@ def _init_status(L, params, ws=1 << 20):
 
 
 @pytest.mark.parametrize("bad", [dict(nx=3), dict(W=0.0), dict(nu_A=-1.0), dict(wall=[1, 0, 1, 1]),
-                                 dict(precision=7), dict(D_psi=float("nan"))])
+                                 dict(precision=7), dict(D_psi=float("nan")),
+                                 # one population buffer beyond the 4 GiB of 32-bit buffer offsets
+                                 dict(nx=8192, ny=4096, precision=0), dict(nx=16384, ny=8192, precision=1)])
 def test_invalid_cases_rejected_before_any_device_call(L, bad):
     rc = _init_status(L, dict(cases.config_small_fp64(), **bad))
     assert rc == lbm.LBM_E_INVAL

@@ -235,6 +235,67 @@ def test_fp16s_centroid(env):
     assert abs(dg["xc"] - do["xc"]) <= 0.05 and abs(dg["yc"] - do["yc"]) <= 0.05
 
 
+# ------------------------------------------------------------------ full-size workloads
+# The benchmark workloads at their real sizes, in the configuration the
+# autotuner picks (as bench.py runs them); the oracle checks sampled cases
+# over the first steps.
+
+def test_fp16s_full_size_sampled(env):
+    """2048x1024 FP16 storage: 40 steps against the oracle over the whole
+    lattice; centroid within 0.05 lu, phi within 1e-3 of its range."""
+    lbm, O = env
+    p = cases.config_precision(cases.FP16S)
+    s = lbm.Solver(p)
+    s.autotune(3)
+    s.step(40)
+    o = O.Oracle(p)
+    o.step(40)
+    dg, do = s.reduce(), o.diag()
+    assert abs(dg["xc"] - do["xc"]) <= 0.05 and abs(dg["yc"] - do["yc"]) <= 0.05
+    err = compare(s.fields(), o.fields(), ("phi", "T", "psi"))
+    assert max(err.values()) <= 1e-3, err
+
+
+def test_batched64_full_size_sampled(env):
+    """The 64 uneven FP32 channels in one launch per step: three of them
+    (smallest, largest, one between) against the oracle after 20 steps."""
+    lbm, O = env
+    ps = cases.config_batched()
+    s = lbm.Solver(ps)
+    s.autotune(3)
+    s.step(20)
+    sizes = [p["nx"] * p["ny"] for p in ps]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), len(ps) // 2})
+    for i in picks:
+        o = O.Oracle(ps[i])
+        o.step(20)
+        err = compare(s.fields(case=i), o.fields(), ("phi", "u", "T", "psi"))
+        assert max(err.values()) <= 1e-5, (i, err)
+        assert s.steps_done(i) == 20
+
+
+def test_large_plus_small_full_size_sampled(env):
+    """4096x2048 FP16-storage channel co-scheduled with 256 FP32 128x64
+    channels: the large case (centroid, phi) and two small ones (FP32 bar)
+    against the oracle after 20 steps."""
+    lbm, O = env
+    ps = cases.config_large_plus_small()
+    s = lbm.Solver(ps)
+    s.autotune(3)
+    s.step(20)
+    o = O.Oracle(ps[0])
+    o.step(20)
+    dg, do = s.reduce(0), o.diag()
+    assert abs(dg["xc"] - do["xc"]) <= 0.05 and abs(dg["yc"] - do["yc"]) <= 0.05
+    err = compare(s.fields(case=0), o.fields(), ("phi", "T", "psi"))
+    assert max(err.values()) <= 1e-3, err
+    for i in (1, len(ps) - 1):
+        o = O.Oracle(ps[i])
+        o.step(20)
+        err = compare(s.fields(case=i), o.fields(), ("phi", "u", "T", "psi"))
+        assert max(err.values()) <= 1e-5, (i, err)
+
+
 # ------------------------------------------------------------------ runtime
 
 def test_batched_cases_equal_single_runs(env):

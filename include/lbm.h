@@ -126,12 +126,17 @@ typedef struct lbm_handle lbm_handle;
 /* Bytes of device workspace needed for these cases (256-byte aligned start). */
 size_t lbm_workspace_bytes(const lbm_case* cases, int32_t ncases);
 
-/* Validate the cases, lay out the workspace, build the tile table and set the
- * initial state of every case (tanh interface plus noise, linear T, psi band,
- * p = 0, u = 0; populations at rest equilibrium).  `workspace` is device
- * memory of at least lbm_workspace_bytes(); `stream` is a hipStream_t (NULL =
- * default stream).  FP64 cases may not be mixed with FP32/FP16S cases in one
- * handle (LBM_E_INVAL).  On success *out receives the handle. */
+/* Validate the cases, lay out the workspace, build the tile and strip tables
+ * and set the initial state of every case (tanh interface plus noise, linear
+ * T, psi band, p = 0, u = 0; populations at rest equilibrium).  `workspace`
+ * is device memory of at least lbm_workspace_bytes(), 256-byte aligned, owned
+ * by the caller and used for everything the library keeps on the device (the
+ * library allocates no device memory); `stream` is a hipStream_t (NULL =
+ * default stream).  LBM_E_INVAL for: FP64 cases mixed with FP32/FP16S cases
+ * in one handle; a case whose population buffer (36 values per node in its
+ * storage type, pitch nx rounded up to 64) exceeds 4 GiB, the reach of the
+ * 32-bit buffer offsets; more than 2^28 nodes in a case.  On success *out
+ * receives the handle. */
 int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t bytes, void* stream,
              lbm_handle** out);
 

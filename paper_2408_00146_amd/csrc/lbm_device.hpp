@@ -860,20 +860,23 @@ constexpr int kStripW = 62;
 
 template <typename R, int BY, bool REFS>
 struct StripSmem {
-    static constexpr int RING = 4 * BY;
+    // rows in flight: references and phi y-1 .. y+2BY+2, p*/T/psi y-1 .. y+2BY;
+    // normals and sigma are written (stage C) only after the previous
+    // collision has finished, so they need 2 BY rows
+    static constexpr int RING = 4 * BY, RING1 = 2 * BY;
     static constexpr int W3 = kStripW + 6, W2 = kStripW + 4, W1 = kStripW + 2;
     R rf[REFS ? RING * W3 : 1];  // phi reference
     R rq[REFS ? RING * W3 : 1];  // psi reference
     R rp[REFS ? RING * W3 : 1];  // p* reference
     R phd[RING * W2];            // phi deviation from its reference
     R phb[REFS ? RING * W2 : 1];
-    double sg[RING * W1];        // sigma (FP64)
+    double sg[RING1 * W1];       // sigma (FP64)
     R ps[RING * W1];             // p* (deviation from its reference with reduced-precision storage)
     R psb[REFS ? RING * W1 : 1]; // p* reference
     R ts[RING * W1];             // T - T_w(column)
     R pq[RING * W1];             // psi
-    R nx[RING * W1];
-    R ny[RING * W1];
+    R nx[RING1 * W1];
+    R ny[RING1 * W1];
 };
 
 // Isotropic gradient (Sec. 3) on ring rows rm (y-1), r0 (y), rp (y+1) at
@@ -906,7 +909,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
     static_assert(REG || BY == 4, "the moment-only row mapping is written for 4 rows per iteration");
     constexpr bool REFS = sizeof(R) == 4;
     using SM = StripSmem<R, BY, REFS>;
-    constexpr int M = SM::RING - 1, W3 = SM::W3, W2 = SM::W2, W1 = SM::W1;
+    constexpr int M = SM::RING - 1, M1 = SM::RING1 - 1, W3 = SM::W3, W2 = SM::W2, W1 = SM::W1;
     constexpr int NT = 64 * BY;
     int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int x0 = u.x0, y0 = u.y0, y1 = u.y1;
@@ -1145,10 +1148,10 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             grad_ring<R, REFS>(sh.phd, sh.phb, ((uy - 1) & M) * W2, (uy & M) * W2, ((uy + 1) & M) * W2, lane + 1, gx, gy);
             R mag = sqrt(gx * gx + gy * gy);
             mag = mag < R(1e-12) ? R(1e-12) : mag;
-            const int e = (uy & M) * W1 + lane;
-            sh.nx[e] = gx / mag;
-            sh.ny[e] = gy / mag;
-            sh.sg[e] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
+            const int e = (uy & M) * W1 + lane, en = (uy & M1) * W1 + lane;
+            sh.nx[en] = gx / mag;
+            sh.ny[en] = gy / mag;
+            sh.sg[en] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
         }
     };
 
@@ -1159,6 +1162,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         if (lane < 1 || lane > kStripW || x >= c.nx || yy >= y1) return;
         const int rm2 = ((yy - 1) & M) * W2, r02 = (yy & M) * W2, rp2 = ((yy + 1) & M) * W2;
         const int rm1 = ((yy - 1) & M) * W1, r01 = (yy & M) * W1, rp1 = ((yy + 1) & M) * W1;
+        const int rmn = ((yy - 1) & M1) * W1, r0n = (yy & M1) * W1, rpn = ((yy + 1) & M1) * W1;
         const int c2 = lane + 1, c1 = lane;
         R gx, gy;
         grad_ring<R, REFS>(sh.phd, sh.phb, rm2, r02, rp2, c2, gx, gy);
@@ -1167,20 +1171,20 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const R phi = phb + phd;
         // 1 - phi from the reference / deviation pair (phi ~ 1 inside a bubble)
         const R omphi = (R(1) - phb) - phd;
-        const R nxv = sh.nx[r01 + c1], nyv = sh.ny[r01 + c1];
+        const R nxv = sh.nx[r0n + c1], nyv = sh.ny[r0n + c1];
         // curvature: isotropic divergence of the normal field
         const R* NX = sh.nx;
         const R* NY = sh.ny;
-        const R kap = (R(4) * (NX[r01 + c1 + 1] - NX[r01 + c1 - 1] + NY[rp1 + c1] - NY[rm1 + c1]) +
-                       (NX[rp1 + c1 + 1] - NX[rp1 + c1 - 1] + NX[rm1 + c1 + 1] - NX[rm1 + c1 - 1]) +
-                       (NY[rp1 + c1 + 1] - NY[rm1 + c1 + 1] + NY[rp1 + c1 - 1] - NY[rm1 + c1 - 1])) *
+        const R kap = (R(4) * (NX[r0n + c1 + 1] - NX[r0n + c1 - 1] + NY[rpn + c1] - NY[rmn + c1]) +
+                       (NX[rpn + c1 + 1] - NX[rpn + c1 - 1] + NX[rmn + c1 + 1] - NX[rmn + c1 - 1]) +
+                       (NY[rpn + c1 + 1] - NY[rmn + c1 + 1] + NY[rpn + c1 - 1] - NY[rmn + c1 - 1])) *
                       R(1.0 / 12.0);
         double dsxd, dsyd;
-        grad_ring<R, false, double>(sh.sg, nullptr, rm1, r01, rp1, c1, dsxd, dsyd);
+        grad_ring<R, false, double>(sh.sg, nullptr, rmn, r0n, rpn, c1, dsxd, dsyd);
         const R dsx = R(dsxd), dsy = R(dsyd);
         R dpx, dpy;
         grad_ring<R, REFS, R>(sh.ps, sh.psb, rm1, r01, rp1, c1, dpx, dpy);
-        const R sig = R(sh.sg[r01 + c1]);
+        const R sig = R(sh.sg[r0n + c1]);
         const R pbase = REFS ? sh.psb[r01 + c1] : R(0);
         const R pstar = pbase + sh.ps[r01 + c1];
 

@@ -193,11 +193,15 @@ int lbm_set_graph(lbm_handle* h, int32_t enable);
 /* Steps done by one case. */
 int64_t lbm_steps_done(lbm_handle* h, int32_t case_id);
 
-/* Average duration (ms) of one step's kernel launches (the step kernel, and
- * for strip configurations the tile kernel of the cases too small for
- * strips) over the steps of the last lbm_step call made while timing was on,
- * measured with HIP events on the handle's stream around each step (timing
- * forces plain launches).  Returns LBM_E_STATE when no timed step exists. */
+/* Step timing with HIP events on the handle's stream.  lbm_set_kernel_timing
+ * mode 1 launches every step on its own between two events (plain launches:
+ * the duration of the step kernels alone); mode 2 records events around each
+ * chunk as lbm_step launches it (captured graphs of up to 100 steps, i.e. the
+ * production path, including the gaps between kernels and the step-counter
+ * update); mode 0 turns timing off.  lbm_kernel_time_ms gives the average
+ * per step over the last lbm_step call made while timing was on and the
+ * number of steps it covered; LBM_E_STATE when no timed call exists,
+ * LBM_E_INVAL for another mode. */
 int lbm_set_kernel_timing(lbm_handle* h, int32_t enable);
 int lbm_kernel_time_ms(lbm_handle* h, double* avg_ms, int64_t* launches);
 

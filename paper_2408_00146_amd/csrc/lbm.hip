@@ -652,7 +652,7 @@ struct lbm_handle {
     int st = ST_F32;  // storage class of the step kernel
     int shape = 1;
     bool use_graph = true;
-    bool timing = false;
+    int timing = 0;  // 0 off, 1 per-step eager launches, 2 per launched chunk
     std::map<int, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> ev;       // pairs around timed step launches
     int64_t timed = 0;
@@ -895,10 +895,12 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
     CHECK_H(h);
     if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
     if (nsteps == 0) return LBM_OK;
-    if (h->timing) {
+    if (h->timing != 0) {
         for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
         h->ev.clear();
         h->timed = 0;
+    }
+    if (h->timing == 1) {
         // eager launches bracketed by events; the step counters advance once per chunk
         const int64_t CHT = 1000;
         for (int64_t c0 = 0; c0 < nsteps; c0 += CHT) {
@@ -925,6 +927,13 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
     int64_t left = nsteps;
     while (left > 0) {
         const int k = (int)std::min(left, CH);
+        if (h->timing == 2) {
+            // events around each chunk as launched (graph replay included)
+            hipEvent_t a;
+            HIPCHK(hipEventCreate(&a));
+            h->ev.push_back(a);
+            HIPCHK(hipEventRecord(a, h->stream));
+        }
         if (h->use_graph) {
             hipGraphExec_t g = nullptr;
             int rc = h->graph_for(k, &g);
@@ -938,9 +947,16 @@ int lbm_step(lbm_handle* h, int64_t nsteps)
             int rc = h->launch_advance(k);
             if (rc != LBM_OK) return rc;
         }
+        if (h->timing == 2) {
+            hipEvent_t b;
+            HIPCHK(hipEventCreate(&b));
+            h->ev.push_back(b);
+            HIPCHK(hipEventRecord(b, h->stream));
+        }
         h->host_advance(k);
         left -= k;
     }
+    if (h->timing == 2) h->timed = nsteps;
     return LBM_OK;
 }
 
@@ -1176,7 +1192,8 @@ int64_t lbm_steps_done(lbm_handle* h, int32_t case_id)
 int lbm_set_kernel_timing(lbm_handle* h, int32_t enable)
 {
     CHECK_H(h);
-    h->timing = enable != 0;
+    if (enable < 0 || enable > 2) return fail(LBM_E_INVAL, "timing mode %d (0, 1 or 2)", (int)enable);
+    h->timing = enable;
     return LBM_OK;
 }
 
@@ -1185,10 +1202,11 @@ int lbm_kernel_time_ms(lbm_handle* h, double* avg_ms, int64_t* launches)
     CHECK_H(h);
     if (h->timed <= 0) return fail(LBM_E_STATE, "no timed lbm_step call");
     HIPCHK(hipStreamSynchronize(h->stream));
+    // event pairs: one per step (mode 1) or one per launched chunk (mode 2)
     double tot = 0;
-    for (int64_t i = 0; i < h->timed; ++i) {
+    for (size_t i = 0; i + 1 < h->ev.size(); i += 2) {
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
         tot += ms;
     }
     if (avg_ms) *avg_ms = tot / (double)h->timed;

@@ -260,8 +260,10 @@ class Solver:
     def set_graph(self, enable: bool):
         _check(lib().lbm_set_graph(self._h, 1 if enable else 0))
 
-    def set_kernel_timing(self, enable: bool):
-        _check(lib().lbm_set_kernel_timing(self._h, 1 if enable else 0))
+    def set_kernel_timing(self, mode):
+        """0/False off, 1/True: each step launched alone between events,
+        2: events around each launched chunk (graph replay)."""
+        _check(lib().lbm_set_kernel_timing(self._h, int(mode)))
 
     def kernel_time_ms(self) -> tuple[float, int]:
         ms, n = C.c_double(), C.c_int64()

@@ -166,7 +166,9 @@ int lbm_load_fields(lbm_handle* h, int32_t case_id, const void* phi, const void*
 int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
 
 /* Step-kernel configuration.  Index i < lbm_tile_count() selects either
- *   kind 0: one workgroup per bx x by tile (tile plus halo staged per step), or
+ *   kind 0: one workgroup per bx x by tile (tile plus halo staged per step;
+ *           with bx * by = 256 each thread owns one node and keeps its
+ *           populations in registers from the moment pass to the collision), or
  *   kind 1: strip marching: one workgroup per strip of bx = 62 columns and
  *           segment of by rows, marching 4 rows per iteration with the
  *           reduced fields of the rows in flight kept in LDS ring buffers;
@@ -178,7 +180,8 @@ int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
  * only the scratch half of the ping-pong pair, so the state is unchanged)
  * and keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
  * lbm_tile_shape / lbm_tile_kind describe an index (LBM_E_INVAL if out of
- * range).  A new handle starts with configuration 0 (64 x 8 tiles). */
+ * range).  A new handle starts with the 64 x 4 tiles (configuration 6) when
+ * all its cases store FP32 or FP64, else with configuration 0 (64 x 8). */
 int lbm_autotune(lbm_handle* h, int32_t trial_steps);
 int lbm_tile_count(void);
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by);

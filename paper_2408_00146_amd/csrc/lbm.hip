@@ -17,12 +17,19 @@
 
 namespace lbm {
 
-// Tile shapes compiled into the library (BX x BY nodes per 256-thread workgroup).
+// Tile shapes compiled into the library (BX x BY nodes per 256-thread workgroup;
+// with 256 nodes, one node per thread, whose populations stay in registers
+// from the moment pass to the collision).
 struct Shape {
     int bx, by;
 };
-constexpr Shape kShapes[] = {{64, 8}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}};
+constexpr Shape kShapes[] = {{64, 8}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}, {64, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+// Initial configuration: 64 x 4 tiles (register-held populations) for FP32
+// and FP64 storage; 64 x 8 for FP16 storage, whose 16-bit loads each occupy
+// a whole VGPR while in flight.
+constexpr int kOwnShape = 6;
+static_assert(kShapes[kOwnShape].bx * kShapes[kOwnShape].by == 256, "one node per thread");
 constexpr int kMacroBX = 64, kMacroBY = 8;
 // Strip-marching configurations: kStripBY rows per iteration (64 x kStripBY
 // threads), segments of kStripSY[j] rows.  Cases narrower than kStripMinNx or
@@ -592,6 +599,7 @@ StepKernel step_kernel_st(int shape)
         case 3: return k_step<ST, 32, 32>;
         case 4: return k_step<ST, 128, 8>;
         case 5: return k_step<ST, 128, 16>;
+        case 6: return k_step<ST, 64, 4>;
     }
     return nullptr;
 }
@@ -807,7 +815,7 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         h->st = any64 ? ST_F64 : (a32 && a16 ? ST_MIXED : (a16 ? ST_F16 : ST_F32));
     }
     h->steps.assign(ncases, 0);
-    h->shape = 0;  // 64 x 8 tiles
+    h->shape = (h->st == ST_F16 || h->st == ST_MIXED) ? 0 : kOwnShape;
 
     size_t o = L.off_pops;
     for (int i = 0; i < ncases; ++i) {
@@ -823,12 +831,16 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         HIPCHK(hipStreamSynchronize(h->stream));
         return LBM_OK;
     };
+    // step tiles of a case in row-major order (measured faster than column
+    // bands of 128 - 512 lattice columns)
+    auto add_tiles = [&](int i, int bx, int by) {
+        for (int y = 0; y < cases[i].ny; y += by)
+            for (int x = 0; x < cases[i].nx; x += bx) tiles.push_back(TileRec{i, x, y, 0});
+    };
     int rc = LBM_OK;
     for (int s = 0; s < kNumShapes && rc == LBM_OK; ++s) {
         tiles.clear();
-        for (int i = 0; i < ncases; ++i)
-            for (int y = 0; y < cases[i].ny; y += kShapes[s].by)
-                for (int x = 0; x < cases[i].nx; x += kShapes[s].bx) tiles.push_back(TileRec{i, x, y, 0});
+        for (int i = 0; i < ncases; ++i) add_tiles(i, kShapes[s].bx, kShapes[s].by);
         rc = upload(h->d_tiles(s));
     }
     for (int j = 0; j < kNumStrip && rc == LBM_OK; ++j) {
@@ -849,9 +861,7 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
     if (rc == LBM_OK) {
         tiles.clear();
         for (int i = 0; i < ncases; ++i)
-            if (!strip_ok(cases[i]))
-                for (int y = 0; y < cases[i].ny; y += kShapes[0].by)
-                    for (int x = 0; x < cases[i].nx; x += kShapes[0].bx) tiles.push_back(TileRec{i, x, y, 0});
+            if (!strip_ok(cases[i])) add_tiles(i, kShapes[0].bx, kShapes[0].by);
         rc = upload(h->d_rest());
     }
     if (rc == LBM_OK) {

@@ -220,55 +220,89 @@ __device__ __forceinline__ Nbr nbr_of(const Ctx<R>& c, int mx, int my)
     return n;
 }
 
-template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
-__device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf,
-                                  const Nbr& nb)
+// A pull in two halves, so that loads can be issued ahead of the storage
+// references they are decoded with: pull_raw selects the slot and loads it,
+// pull_fix decodes it and applies the wall rules.
+//
+// Branch-free general case: the source node or, beyond a wall, the node
+// itself in the opposite direction is selected per lane, so that the nine
+// loads of a set can be issued together.  A y wall wins over an x wall
+// (corner links); the wall a direction can cross is fixed by its sign: e_y > 0
+// pulls from below (side 2), e_x > 0 from the left (side 0).
+template <int A>
+struct Link {
+    static constexpr int EX = ex(A), EY = ey(A);
+    int sx;
+    bool wy, wx;
+    __device__ __forceinline__ Link(const Nbr& nb, int mx)
+    {
+        sx = EX > 0 ? nb.sxm : (EX < 0 ? nb.sxp : mx);
+        wy = EY > 0 ? nb.wym : (EY < 0 ? nb.wyp : false);
+        wx = !wy && (EX > 0 ? nb.wxm : (EX < 0 ? nb.wxp : false));
+    }
+    __device__ __forceinline__ bool wall() const { return wy || wx; }
+};
+
+template <int SET, int A, bool INT, typename S, typename R>
+__device__ __forceinline__ S pull_raw(const Ctx<R>& c, View src, int mx, int my, const Nbr& nb)
 {
     constexpr int EX = ex(A), EY = ey(A);
     constexpr uint32_t E = sizeof(S);
-    constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q || SET == SET_G);
-    const R w = R(wt(A));
     if (INT) {
         // shift of the source folded into the scalar offset (never negative: plane >= pitch + 1)
         const uint32_t v = (uint32_t)(my * c.pitch + mx) * E;
         const uint32_t so = (uint32_t)((SET * 9 + A) * c.plane - EY * c.pitch - EX) * E;
-        R val = dec<S, R>(Mem<S>::ld(src.r, v, so), c.inv_scale);
+        return Mem<S>::ld(src.r, v, so);
+    }
+    const Link<A> l(nb, mx);
+    const int rs = EY > 0 ? nb.rym : (EY < 0 ? nb.ryp : nb.ry0);
+    const bool wall = l.wall();
+    const uint32_t node = wall ? (uint32_t)(nb.ry0 + mx) : (uint32_t)(rs + l.sx);
+    const uint32_t pln = wall ? (uint32_t)((SET * 9 + opp(A)) * c.plane) : (uint32_t)((SET * 9 + A) * c.plane);
+    return Mem<S>::ld(src.r, (node + pln) * E, 0u);
+}
+
+template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
+__device__ __forceinline__ R pull_fix(const Ctx<R>& c, S raw, int ux, int uy, int mx, R base, const RF& rf,
+                                      const Nbr& nb)
+{
+    constexpr int EX = ex(A), EY = ey(A);
+    constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q || SET == SET_G);
+    const R w = R(wt(A));
+    R val = dec<S, R>(raw, c.inv_scale);
+    if (INT) {
         if (NODE_REF) val += w * (rf(ux - EX, uy - EY) - base);
         if (REFS && SET == SET_H && EX != 0) val -= w * c.gradT * R(EX);  // linear-law reference of column mx - ex
         return val;
     }
-    // Branch-free: the source node or, beyond a wall, the node itself in the
-    // opposite direction is selected per lane, so that the nine loads of a
-    // set can be issued together.  A y wall wins over an x wall (corner links);
-    // the wall a direction can cross is fixed by its sign: e_y > 0 pulls from
-    // below (side 2), e_x > 0 from the left (side 0).
-    const int sx = EX > 0 ? nb.sxm : (EX < 0 ? nb.sxp : mx);
-    const int rs = EY > 0 ? nb.rym : (EY < 0 ? nb.ryp : nb.ry0);
-    const bool wy = EY > 0 ? nb.wym : (EY < 0 ? nb.wyp : false);
-    const bool wx = !wy && (EX > 0 ? nb.wxm : (EX < 0 ? nb.wxp : false));
-    const bool wall = wy || wx;
+    const Link<A> l(nb, mx);
+    const bool wall = l.wall();
     constexpr int YS = EY > 0 ? 2 : 3, XS = EX > 0 ? 0 : 1;
-    constexpr int B = opp(A);
-    const uint32_t node = wall ? (uint32_t)(nb.ry0 + mx) : (uint32_t)(rs + sx);
-    const uint32_t pln = wall ? (uint32_t)((SET * 9 + B) * c.plane) : (uint32_t)((SET * 9 + A) * c.plane);
-    R val = dec<S, R>(Mem<S>::ld(src.r, (node + pln) * E, 0u), c.inv_scale);
     if (NODE_REF) {
         // beyond a wall the slot is the node's own, stored against its own reference
         const int rx = wall ? ux : ux - EX, ry = wall ? uy : uy - EY;
         val += w * (rf(rx, ry) - base);
     }
     // linear-law reference of column sx (not at a wall, where the slot is the node's own)
-    if (REFS && SET == SET_H && EX != 0) val += wall ? R(0) : w * c.gradT * R(sx - mx);
+    if (REFS && SET == SET_H && EX != 0) val += wall ? R(0) : w * c.gradT * R(l.sx - mx);
     if (SET == SET_H) {
         // X_w - base; with the linear-law reference exactly -gradT ex / 2
         const R d = REFS ? R(-0.5) * c.gradT * R(EX) : c.Tlaw(R(mx) - R(0.5) * R(EX)) - base;
-        if ((wy && c.t_dir(YS)) || (wx && c.t_dir(XS))) val = -val + R(2) * w * d;
+        if ((l.wy && c.t_dir(YS)) || (l.wx && c.t_dir(XS))) val = -val + R(2) * w * d;
     }
     if (SET == SET_Q) {
-        if (wy && c.p_dir(YS)) val = -val + R(2) * w * (c.psi_wall_sel(YS) - base);
-        else if (wx && c.p_dir(XS)) val = -val + R(2) * w * (c.psi_wall_sel(XS) - base);
+        if (l.wy && c.p_dir(YS)) val = -val + R(2) * w * (c.psi_wall_sel(YS) - base);
+        else if (l.wx && c.p_dir(XS)) val = -val + R(2) * w * (c.psi_wall_sel(XS) - base);
     }
     return val;
+}
+
+template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
+__device__ __forceinline__ R pull(const Ctx<R>& c, View src, int ux, int uy, int mx, int my, R base, const RF& rf,
+                                  const Nbr& nb)
+{
+    return pull_fix<SET, A, INT, REFS, S, R>(c, pull_raw<SET, A, INT, S, R>(c, src, mx, my, nb), ux, uy, mx, base, rf,
+                                             nb);
 }
 
 template <int SET, bool INT, bool REFS, typename S, typename R, typename RF>
@@ -288,6 +322,38 @@ __device__ __forceinline__ void pull9(const Ctx<R>& c, View src, int ux, int uy,
     // near walls / periodic seams: keep the scheduler from hoisting the next
     // set's loads above this one (nine loads in flight, no spills)
     if (!INT) __builtin_amdgcn_sched_barrier(0);
+}
+
+// The two halves of pull9 (the Nbr of a general pull is recomputed in the fix).
+template <int SET, bool INT, typename S, typename R>
+__device__ __forceinline__ void raw9(const Ctx<R>& c, View src, int mx, int my, S r[9])
+{
+    const Nbr nb = INT ? Nbr{} : nbr_of(c, mx, my);
+    r[0] = pull_raw<SET, 0, INT, S, R>(c, src, mx, my, nb);
+    r[1] = pull_raw<SET, 1, INT, S, R>(c, src, mx, my, nb);
+    r[2] = pull_raw<SET, 2, INT, S, R>(c, src, mx, my, nb);
+    r[3] = pull_raw<SET, 3, INT, S, R>(c, src, mx, my, nb);
+    r[4] = pull_raw<SET, 4, INT, S, R>(c, src, mx, my, nb);
+    r[5] = pull_raw<SET, 5, INT, S, R>(c, src, mx, my, nb);
+    r[6] = pull_raw<SET, 6, INT, S, R>(c, src, mx, my, nb);
+    r[7] = pull_raw<SET, 7, INT, S, R>(c, src, mx, my, nb);
+    r[8] = pull_raw<SET, 8, INT, S, R>(c, src, mx, my, nb);
+}
+
+template <int SET, bool INT, bool REFS, typename S, typename R, typename RF>
+__device__ __forceinline__ void fix9(const Ctx<R>& c, const S r[9], int ux, int uy, int mx, int my, R base,
+                                     const RF& rf, R v[9])
+{
+    const Nbr nb = INT ? Nbr{} : nbr_of(c, mx, my);
+    v[0] = pull_fix<SET, 0, INT, REFS, S, R>(c, r[0], ux, uy, mx, base, rf, nb);
+    v[1] = pull_fix<SET, 1, INT, REFS, S, R>(c, r[1], ux, uy, mx, base, rf, nb);
+    v[2] = pull_fix<SET, 2, INT, REFS, S, R>(c, r[2], ux, uy, mx, base, rf, nb);
+    v[3] = pull_fix<SET, 3, INT, REFS, S, R>(c, r[3], ux, uy, mx, base, rf, nb);
+    v[4] = pull_fix<SET, 4, INT, REFS, S, R>(c, r[4], ux, uy, mx, base, rf, nb);
+    v[5] = pull_fix<SET, 5, INT, REFS, S, R>(c, r[5], ux, uy, mx, base, rf, nb);
+    v[6] = pull_fix<SET, 6, INT, REFS, S, R>(c, r[6], ux, uy, mx, base, rf, nb);
+    v[7] = pull_fix<SET, 7, INT, REFS, S, R>(c, r[7], ux, uy, mx, base, rf, nb);
+    v[8] = pull_fix<SET, 8, INT, REFS, S, R>(c, r[8], ux, uy, mx, base, rf, nb);
 }
 
 // Store the 9 post-collision populations of a set at node offset v (bytes).
@@ -500,6 +566,11 @@ __device__ __forceinline__ void collide_g_dev(R g[9], R pstar, R jx, R jy, R pd,
 }
 
 // ------------------------------------------------------------ tile body
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
 enum { MODE_STEP = 0, MODE_MACRO = 1 };
 
 // Output of the macro (diagnostic / export) mode.
@@ -556,6 +627,11 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
 {
     constexpr bool REFS = sizeof(R) == 4;
     constexpr int NT = 256;
+    constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
+    // population loads of phase 1a issued before the storage references are
+    // committed (one own node per thread; 16-bit values would each hold a
+    // whole VGPR while in flight, which spills)
+    constexpr bool EARLY = OWN1 && sizeof(S) >= 4;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
@@ -573,39 +649,54 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     auto ghostx = [&](int u) { return !INT && c.wallx && (u < 0 || u >= c.nx); };
     auto ghosty = [&](int u) { return !INT && c.wally && (u < 0 || u >= c.ny); };
 
-    // ---- phase 0: storage references on tile + 3 halo
-    if (REFS) {
-        for (int k = tid; k < W3 * H3; k += NT) {
+    // ---- phase 0: storage references on tile + 3 halo.  Every load of a
+    // thread is issued before the first is consumed: slots without a lattice
+    // node read node 0 and keep 0 (no branch around the loads).  With one own
+    // node per thread the population loads of phase 1a are issued before the
+    // references are committed to LDS.
+    constexpr int NI = REFS ? (W3 * H3 + NT - 1) / NT : 1;
+    __half ra[NI], rb[NI], rd[NI];
+    bool rok[NI];
+    auto ref_issue = [&]() {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = tid + i * NT;
             const int ux = x0 - 3 + k % W3, uy = y0 - 3 + k / W3;
-            R a = R(0), b = R(0), d = R(0);
-            if (!ghostx(ux) && !ghosty(uy)) {
-                int mx = wrapx(ux), my = wrapy(uy);
-                // beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
-                if (mx >= 0 && mx < c.nx && my >= 0 && my < c.ny) {
-                    const uint32_t ob = (uint32_t)(my * c.pitch + mx) * 2u;
-                    a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
-                    b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
-                    d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
-                }
+            const int mx = wrapx(ux), my = wrapy(uy);
+            // ghosts, and beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
+            rok[i] = k < W3 * H3 && !ghostx(ux) && !ghosty(uy) && mx >= 0 && mx < c.nx && my >= 0 && my < c.ny;
+            const uint32_t ob = rok[i] ? (uint32_t)(my * c.pitch + mx) * 2u : 0u;
+            ra[i] = Mem<__half>::ld(rsrc, ob, 0);
+            rb[i] = Mem<__half>::ld(rsrc, ob, rplane_b);
+            rd[i] = Mem<__half>::ld(rsrc, ob, 2u * rplane_b);
+        }
+    };
+    auto ref_commit = [&]() {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int k = tid + i * NT;
+            if (k < W3 * H3) {
+                sh.rf[k] = rok[i] ? R(__half2float(ra[i])) : R(0);
+                sh.rq[k] = rok[i] ? R(__half2float(rb[i])) : R(0);
+                sh.rp[k] = rok[i] ? R(__half2float(rd[i])) : R(0);
             }
-            sh.rf[k] = a;
-            sh.rq[k] = b;
-            sh.rp[k] = d;
         }
         __syncthreads();
-    }
+    };
+    if (REFS) ref_issue();
+    if (REFS && !EARLY) ref_commit();
 
     // ---- phase 1a: phi on tile + 2 halo; p*, T, psi on tile + 1 halo (lattice nodes)
     // (tid is made opaque at each phase so that no index math is kept live across phases)
     asm volatile("" : "+v"(tid));
-    for (int k = tid; k < W2 * H2; k += NT) {
-        const int lx = k % W2, ly = k / W2;
+    // moments of E2 slot (lx, ly); in1: the slot lies in E1 as well
+    auto slot_moments = [&](int lx, int ly, auto in1c) {
+        constexpr bool in1 = decltype(in1c)::value;
+        const int k = ly * W2 + lx, e1 = (ly - 1) * W1 + (lx - 1);
         const int ux = x0 - 2 + lx, uy = y0 - 2 + ly;
-        const bool in1 = lx >= 1 && lx <= BX + 2 && ly >= 1 && ly <= BY + 2;
-        const int e1 = (ly - 1) * W1 + (lx - 1);
         const int mx = wrapx(ux), my = wrapy(uy);
         // ghosts are filled in phase 1b; beyond one wrap no live node reads the slot
-        if (ghostx(ux) || ghosty(uy) || (!INT && (mx < 0 || mx >= c.nx || my < 0 || my >= c.ny))) continue;
+        if (ghostx(ux) || ghosty(uy) || (!INT && (mx < 0 || mx >= c.nx || my < 0 || my >= c.ny))) return;
         R v[9];
         const R bf = ref_f(ux, uy);
         pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, v);
@@ -623,6 +714,158 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R bq = ref_q(ux, uy);
             pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, v);
             sh.pq[e1] = bq + sum9(v);
+        }
+    };
+    // OWN1 (one own node per thread): the thread's own node is pulled once,
+    // its 36 populations stay in registers until its collision
+    R F[9], G[9], H[9], Q[9];
+    if constexpr (OWN1) {
+        // Loads first, for every slot of the thread: its own node (36), ring
+        // slot tid (E1 ring: 36, outer E2 ring: 9) and ring slot tid + NT
+        // (outer ring: 9); the sums and LDS writes follow.
+        constexpr int NR1 = 2 * W1 + 2 * BY, NR2 = 2 * W2 + 2 * (BY + 2), NR = NR1 + NR2;
+        static_assert(NR1 <= NT && NR <= 2 * NT && NR - NT <= NR2, "ring slots per thread");
+        // E2 coordinates of ring slot r: the E1 ring first, then the outer E2 ring
+        auto ring_slot = [&](int r, int& lx, int& ly) {
+            if (r < 2 * W1) {
+                ly = r < W1 ? 1 : BY + 2;
+                lx = 1 + (r < W1 ? r : r - W1);
+            } else if (r < NR1) {
+                const int m = r - 2 * W1;
+                ly = 2 + (m >> 1);
+                lx = (m & 1) ? BX + 2 : 1;
+            } else if (r < NR1 + 2 * W2) {
+                const int m = r - NR1;
+                ly = m < W2 ? 0 : BY + 3;
+                lx = m < W2 ? m : m - W2;
+            } else {
+                const int m = r - NR1 - 2 * W2;
+                ly = 1 + (m >> 1);
+                lx = (m & 1) ? BX + 3 : 0;
+            }
+        };
+        // lattice node of E2 slot (lx, ly); false for ghosts (filled in
+        // phase 1b) and beyond one wrap (read by no live node)
+        auto node_of = [&](int lx, int ly, int& ux, int& uy, int& mx, int& my) {
+            ux = x0 - 2 + lx;
+            uy = y0 - 2 + ly;
+            mx = wrapx(ux);
+            my = wrapy(uy);
+            return !(ghostx(ux) || ghosty(uy) || (!INT && (mx < 0 || mx >= c.nx || my < 0 || my >= c.ny)));
+        };
+        int ux, uy, mx, my, alx, aly, aux, auy, amx, amy, blx, bly, bux, buy, bmx, bmy;
+        const int olx = tid % BX + 2, oly = tid / BX + 2;
+        const bool own_ok = node_of(olx, oly, ux, uy, mx, my);
+        ring_slot(tid, alx, aly);
+        const bool a_ok = node_of(alx, aly, aux, auy, amx, amy), a_e1 = tid < NR1;
+        const bool b_has = tid + NT < NR;
+        ring_slot(b_has ? tid + NT : NR - 1, blx, bly);
+        const bool b_ok = b_has && node_of(blx, bly, bux, buy, bmx, bmy);
+        // sums and LDS writes
+        auto put_f = [&](int lx, int ly, R base, const R* v) {
+            const int k = ly * W2 + lx;
+            sh.phd[k] = sum9(v);
+            if (REFS) sh.phb[k] = base;
+        };
+        auto put_ghq = [&](int lx, int ly, int sux, int smx, R pb, R qb, const R* vg, const R* vh, const R* vq) {
+            const int e1 = (ly - 1) * W1 + (lx - 1);
+            sh.ps[e1] = sum9(vg);
+            if (REFS) sh.psb[e1] = pb;
+            // T - T_w(ux): with the linear-law reference exactly gradT (mx - ux) + sum
+            sh.ts[e1] = REFS ? c.gradT * R(smx - sux) + sum9(vh) : R((double)sum9(vh) - c.Tlaw_d((double)sux));
+            sh.pq[e1] = qb + sum9(vq);
+        };
+        if constexpr (EARLY) {
+            // loads, then the references, then the decoding
+            S rF[9], rG[9], rH[9], rQ[9], rA[9], rAG[9], rAH[9], rAQ[9], rB[9];
+            if (own_ok) {
+                raw9<SET_F, INT, S, R>(c, src, mx, my, rF);
+                raw9<SET_G, INT, S, R>(c, src, mx, my, rG);
+                raw9<SET_H, INT, S, R>(c, src, mx, my, rH);
+                raw9<SET_Q, INT, S, R>(c, src, mx, my, rQ);
+            }
+            if (a_ok) raw9<SET_F, INT, S, R>(c, src, amx, amy, rA);
+            if (a_ok && a_e1) {
+                raw9<SET_G, INT, S, R>(c, src, amx, amy, rAG);
+                raw9<SET_H, INT, S, R>(c, src, amx, amy, rAH);
+                raw9<SET_Q, INT, S, R>(c, src, amx, amy, rAQ);
+            }
+            if (b_ok) raw9<SET_F, INT, S, R>(c, src, bmx, bmy, rB);
+            if (REFS) ref_commit();
+            const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
+            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+            if (own_ok) {
+                fix9<SET_F, INT, REFS, S, R>(c, rF, ux, uy, mx, my, bf, ref_f, F);
+                fix9<SET_G, INT, REFS, S, R>(c, rG, ux, uy, mx, my, bp, ref_p, G);
+                fix9<SET_H, INT, REFS, S, R>(c, rH, ux, uy, mx, my, bh, no_ref, H);
+                fix9<SET_Q, INT, REFS, S, R>(c, rQ, ux, uy, mx, my, bq, ref_q, Q);
+            }
+            const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
+            const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
+            R VA[9], VG[9], VH[9], VQ[9], VB[9];
+            if (a_ok) fix9<SET_F, INT, REFS, S, R>(c, rA, aux, auy, amx, amy, abf, ref_f, VA);
+            if (a_ok && a_e1) {
+                fix9<SET_G, INT, REFS, S, R>(c, rAG, aux, auy, amx, amy, abp, ref_p, VG);
+                fix9<SET_H, INT, REFS, S, R>(c, rAH, aux, auy, amx, amy, abh, no_ref, VH);
+                fix9<SET_Q, INT, REFS, S, R>(c, rAQ, aux, auy, amx, amy, abq, ref_q, VQ);
+            }
+            const R bbf = ref_f(bux, buy);
+            if (b_ok) fix9<SET_F, INT, REFS, S, R>(c, rB, bux, buy, bmx, bmy, bbf, ref_f, VB);
+            if (own_ok) {
+                put_f(olx, oly, bf, F);
+                put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
+            }
+            if (a_ok) {
+                put_f(alx, aly, abf, VA);
+                if (a_e1) put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
+            }
+            if (b_ok) put_f(blx, bly, bbf, VB);
+        } else {
+            const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
+            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+            if (own_ok) {
+                pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, F);
+                pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, G);
+                pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, H);
+                pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
+            }
+            const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
+            const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
+            R VA[9], VG[9], VH[9], VQ[9], VB[9];
+            if (a_ok) pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
+            if (a_ok && a_e1) {
+                pull9<SET_G, INT, REFS, S>(c, src, aux, auy, amx, amy, abp, ref_p, VG);
+                pull9<SET_H, INT, REFS, S>(c, src, aux, auy, amx, amy, abh, no_ref, VH);
+                pull9<SET_Q, INT, REFS, S>(c, src, aux, auy, amx, amy, abq, ref_q, VQ);
+            }
+            const R bbf = ref_f(bux, buy);
+            if (b_ok) pull9<SET_F, INT, REFS, S>(c, src, bux, buy, bmx, bmy, bbf, ref_f, VB);
+            if (own_ok) {
+                put_f(olx, oly, bf, F);
+                put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
+            }
+            if (a_ok) {
+                put_f(alx, aly, abf, VA);
+                if (a_e1) put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
+            }
+            if (b_ok) put_f(blx, bly, bbf, VB);
+        }
+    } else {
+        // E1 slots (all four sets, their 36 loads issued together), then the
+        // outer E2 ring (phi only)
+        for (int k = tid; k < W1 * H1; k += NT) slot_moments(k % W1 + 1, k / W1 + 1, BoolC<true>{});
+        constexpr int NR2 = 2 * W2 + 2 * (BY + 2);
+        for (int r = tid; r < NR2; r += NT) {
+            int lx, ly;
+            if (r < 2 * W2) {
+                ly = r < W2 ? 0 : BY + 3;
+                lx = r < W2 ? r : r - W2;
+            } else {
+                const int m = r - 2 * W2;
+                ly = 1 + (m >> 1);
+                lx = (m & 1) ? BX + 3 : 0;
+            }
+            slot_moments(lx, ly, BoolC<false>{});
         }
     }
     __syncthreads();
@@ -740,7 +983,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
 
         // g: momentum, velocity and pressure
         R g[9];
-        pull9<SET_G, INT, REFS, S>(c, src, x, y, x, y, pbase, ref_p, g);
+        if constexpr (OWN1) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) g[a] = G[a];
+        } else {
+            pull9<SET_G, INT, REFS, S>(c, src, x, y, x, y, pbase, ref_p, g);
+        }
         const R jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
         const R jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
         const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
@@ -791,39 +1039,57 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         }
 
         const uint32_t o = (uint32_t)(y * c.pitch + x);
-        // the new p* reference is the FP16-rounded p* of this node
+        // the new storage references are the FP16-rounded phi, psi, p* of this node
         const R nbp = REFS ? R(__half2float(__float2half_rn((float)pstar))) : R(0);
-        if (REFS) {
-            const R pd = (pbase - nbp) + sh.ps[p1] + R(0.5) * (Fpx * ux + Fpy * uy);
-            collide_g_dev(g, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
-        } else {
-            collide_g(g, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
-        }
-        store9<SET_G, S>(c, dst, o * (uint32_t)sizeof(S), g);
-
-        // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
-        // the new storage reference is the FP16-rounded phi of this node
-        R f[9];
-        pull9<SET_F, INT, REFS, S>(c, src, x, y, x, y, phb, ref_f, f);
-        const R mt = c.Mphi * R(4) * phi * omphi / c.W;
         const R nbf = REFS ? R(__half2float(__float2half_rn((float)phi))) : R(0);
-        collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
-        store9<SET_F, S>(c, dst, o * (uint32_t)sizeof(S), f);
-
+        auto do_g = [&](R* gg) {
+            if (REFS) {
+                const R pd = (pbase - nbp) + sh.ps[p1] + R(0.5) * (Fpx * ux + Fpy * uy);
+                collide_g_dev(gg, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+            } else {
+                collide_g(gg, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+            }
+            store9<SET_G, S>(c, dst, o * (uint32_t)sizeof(S), gg);
+        };
+        // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W
+        auto do_f = [&](R* f) {
+            const R mt = c.Mphi * R(4) * phi * omphi / c.W;
+            collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
+            store9<SET_F, S>(c, dst, o * (uint32_t)sizeof(S), f);
+        };
         // h: temperature
-        R hh[9];
-        pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hh);
-        collide_ad(hh, bh, bh, R(0), R(0), omT, ux, uy);
-        store9<SET_H, S>(c, dst, o * (uint32_t)sizeof(S), hh);
-
+        auto do_h = [&](R* hh) {
+            collide_ad(hh, bh, bh, R(0), R(0), omT, ux, uy);
+            store9<SET_H, S>(c, dst, o * (uint32_t)sizeof(S), hh);
+        };
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
-        R qq[9];
-        pull9<SET_Q, INT, REFS, S>(c, src, x, y, x, y, bq, ref_q, qq);
-        const R psi = bq + sum9(qq);
-        const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
-        const R nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
-        collide_ad(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
-        store9<SET_Q, S>(c, dst, o * (uint32_t)sizeof(S), qq);
+        R nbq = R(0);
+        auto do_q = [&](R* qq) {
+            const R psi = bq + sum9(qq);
+            const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
+            nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
+            collide_ad(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
+            store9<SET_Q, S>(c, dst, o * (uint32_t)sizeof(S), qq);
+        };
+        if constexpr (OWN1) {
+            // held sets first, g (the largest collision) last: fewer values live at once
+            do_f(F);
+            do_h(H);
+            do_q(Q);
+            do_g(g);
+        } else {
+            // each set pulled right before its collision
+            do_g(g);
+            R f[9];
+            pull9<SET_F, INT, REFS, S>(c, src, x, y, x, y, phb, ref_f, f);
+            do_f(f);
+            R hh[9];
+            pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hh);
+            do_h(hh);
+            R qq[9];
+            pull9<SET_Q, INT, REFS, S>(c, src, x, y, x, y, bq, ref_q, qq);
+            do_q(qq);
+        }
         if (REFS) {
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
             Mem<__half>::st(__float2half_rn((float)nbq), rdst, o * 2u, rplane_b);
@@ -893,11 +1159,6 @@ __device__ __forceinline__ void grad_ring(const T* D, const T* B, int rm, int r0
     gx = dx * T(1.0 / 12.0);
     gy = dy * T(1.0 / 12.0);
 }
-
-template <bool B>
-struct BoolC {
-    static constexpr bool value = B;
-};
 
 // REG = true: each node's populations stay in registers from B to D;
 // REG = false: B only reduces moments (rows spread evenly over the waves) and

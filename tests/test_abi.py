@@ -71,7 +71,7 @@ def test_tile_table(L):
     assert len(shapes) == len(kinds) == L.lbm_tile_count()
     tiles = [s for s, k in zip(shapes, kinds) if k == "tile"]
     strips = [s for s, k in zip(shapes, kinds) if k == "strip"]
-    assert (64, 16) in tiles and all(bx * by >= 256 for bx, by in tiles)
+    assert (64, 16) in tiles and (64, 4) in tiles and all(bx * by >= 256 for bx, by in tiles)
     # strips: 62 columns, segments a multiple of the 4 rows marched per iteration
     assert strips and all(bx == 62 and by % 4 == 0 for bx, by in strips)
     assert kinds[0] == "tile"

@@ -81,8 +81,9 @@ __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
 
 template <int ST, int BX, int BY>
-// Three workgroups per CU (<= 168 VGPRs) for the FP32/FP16 kernels; FP64 keeps two.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 2 : 3))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
+// Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the 64 x 4
+// FP32/FP16 tiles, three (<= 168) for the other FP32/FP16 tiles, two for FP64.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 2 : (BX * BY == 256 ? 4 : 3)))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
                                               int ntiles, const int64_t* __restrict__ steps, int t)
 {
     using R = typename std::conditional<ST == ST_F64, double, float>::type;
@@ -424,10 +425,16 @@ size_t elem_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
-size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * pitch_of(c.nx) * c.ny * elem_bytes(c.precision)); }
+// Nodes per population / reference plane: ny rows of the pitch plus kPlanePad
+// nodes, so that the 36 planes of a buffer do not start at one power-of-two
+// stride.
+constexpr int kPlanePad = 64;
+int64_t plane_of(const lbm_case& c) { return (int64_t)c.ny * pitch_of(c.nx) + kPlanePad; }
+
+size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * plane_of(c) * elem_bytes(c.precision)); }
 
 // Per-node storage references (phi, psi, p*) of reduced-precision cases: 3 FP16 planes per buffer.
-size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)3 * pitch_of(c.nx) * c.ny * 2); }
+size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)3 * plane_of(c) * 2); }
 
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
 
@@ -561,7 +568,7 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
     d.grav = c.gravity;
     d.scale = c.precision == LBM_FP16S ? 1024.0 : 1.0;
     d.inv_scale = 1.0 / d.scale;
-    d.plane = (int64_t)c.ny * d.pitch;
+    d.plane = plane_of(c);
     d.max_steps = c.max_steps;
     d.pop_bytes = (uint32_t)case_pop_bytes(c);
     d.ref_bytes = (uint32_t)case_ref_bytes(c);

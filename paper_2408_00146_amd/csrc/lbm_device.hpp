@@ -629,9 +629,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr int NT = 256;
     constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
     // population loads of phase 1a issued before the storage references are
-    // committed (one own node per thread; 16-bit values would each hold a
-    // whole VGPR while in flight, which spills)
-    constexpr bool EARLY = OWN1 && sizeof(S) >= 4;
+    // committed (one own node per thread, interior tiles; 16-bit values would
+    // each hold a whole VGPR while in flight, which spills)
+    constexpr bool EARLY = OWN1 && INT && sizeof(S) >= 4;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
@@ -792,6 +792,27 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             }
             if (b_ok) raw9<SET_F, INT, S, R>(c, src, bmx, bmy, rB);
             if (REFS) ref_commit();
+            // ring slots first (their values die in the sums), the own node last
+            {
+                const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
+                const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
+                R VA[9], VG[9], VH[9], VQ[9], VB[9];
+                if (a_ok) {
+                    fix9<SET_F, INT, REFS, S, R>(c, rA, aux, auy, amx, amy, abf, ref_f, VA);
+                    put_f(alx, aly, abf, VA);
+                }
+                if (a_ok && a_e1) {
+                    fix9<SET_G, INT, REFS, S, R>(c, rAG, aux, auy, amx, amy, abp, ref_p, VG);
+                    fix9<SET_H, INT, REFS, S, R>(c, rAH, aux, auy, amx, amy, abh, no_ref, VH);
+                    fix9<SET_Q, INT, REFS, S, R>(c, rAQ, aux, auy, amx, amy, abq, ref_q, VQ);
+                    put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
+                }
+                const R bbf = ref_f(bux, buy);
+                if (b_ok) {
+                    fix9<SET_F, INT, REFS, S, R>(c, rB, bux, buy, bmx, bmy, bbf, ref_f, VB);
+                    put_f(blx, bly, bbf, VB);
+                }
+            }
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             if (own_ok) {
@@ -799,28 +820,29 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 fix9<SET_G, INT, REFS, S, R>(c, rG, ux, uy, mx, my, bp, ref_p, G);
                 fix9<SET_H, INT, REFS, S, R>(c, rH, ux, uy, mx, my, bh, no_ref, H);
                 fix9<SET_Q, INT, REFS, S, R>(c, rQ, ux, uy, mx, my, bq, ref_q, Q);
-            }
-            const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
-            const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
-            R VA[9], VG[9], VH[9], VQ[9], VB[9];
-            if (a_ok) fix9<SET_F, INT, REFS, S, R>(c, rA, aux, auy, amx, amy, abf, ref_f, VA);
-            if (a_ok && a_e1) {
-                fix9<SET_G, INT, REFS, S, R>(c, rAG, aux, auy, amx, amy, abp, ref_p, VG);
-                fix9<SET_H, INT, REFS, S, R>(c, rAH, aux, auy, amx, amy, abh, no_ref, VH);
-                fix9<SET_Q, INT, REFS, S, R>(c, rAQ, aux, auy, amx, amy, abq, ref_q, VQ);
-            }
-            const R bbf = ref_f(bux, buy);
-            if (b_ok) fix9<SET_F, INT, REFS, S, R>(c, rB, bux, buy, bmx, bmy, bbf, ref_f, VB);
-            if (own_ok) {
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
             }
-            if (a_ok) {
-                put_f(alx, aly, abf, VA);
-                if (a_e1) put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
-            }
-            if (b_ok) put_f(blx, bly, bbf, VB);
         } else {
+            // ring slots first, then the own node (fewer values live at once)
+            {
+                const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
+                const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
+                R VA[9], VG[9], VH[9], VQ[9], VB[9];
+                if (a_ok) pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
+                if (a_ok && a_e1) {
+                    pull9<SET_G, INT, REFS, S>(c, src, aux, auy, amx, amy, abp, ref_p, VG);
+                    pull9<SET_H, INT, REFS, S>(c, src, aux, auy, amx, amy, abh, no_ref, VH);
+                    pull9<SET_Q, INT, REFS, S>(c, src, aux, auy, amx, amy, abq, ref_q, VQ);
+                }
+                const R bbf = ref_f(bux, buy);
+                if (b_ok) pull9<SET_F, INT, REFS, S>(c, src, bux, buy, bmx, bmy, bbf, ref_f, VB);
+                if (a_ok) {
+                    put_f(alx, aly, abf, VA);
+                    if (a_e1) put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
+                }
+                if (b_ok) put_f(blx, bly, bbf, VB);
+            }
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             if (own_ok) {
@@ -828,27 +850,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, G);
                 pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, H);
                 pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
-            }
-            const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
-            const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
-            R VA[9], VG[9], VH[9], VQ[9], VB[9];
-            if (a_ok) pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
-            if (a_ok && a_e1) {
-                pull9<SET_G, INT, REFS, S>(c, src, aux, auy, amx, amy, abp, ref_p, VG);
-                pull9<SET_H, INT, REFS, S>(c, src, aux, auy, amx, amy, abh, no_ref, VH);
-                pull9<SET_Q, INT, REFS, S>(c, src, aux, auy, amx, amy, abq, ref_q, VQ);
-            }
-            const R bbf = ref_f(bux, buy);
-            if (b_ok) pull9<SET_F, INT, REFS, S>(c, src, bux, buy, bmx, bmy, bbf, ref_f, VB);
-            if (own_ok) {
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
             }
-            if (a_ok) {
-                put_f(alx, aly, abf, VA);
-                if (a_e1) put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
-            }
-            if (b_ok) put_f(blx, bly, bbf, VB);
         }
     } else {
         // E1 slots (all four sets, their 36 loads issued together), then the

@@ -73,7 +73,7 @@ def measured_traffic(workload: str, config: str) -> int | None:
     workload and kernel configuration ("tile 64x8", "strip 62x16"), or None
     when there is none or the kernel sources have changed since the counters
     were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_{config.replace(' ', '')}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     kv = {}

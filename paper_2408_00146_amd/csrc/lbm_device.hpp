@@ -378,14 +378,17 @@ __device__ __forceinline__ R sum9(const R v[9])
 // Surface tension (Sec. 2.1): law 1 as printed, law 0 the multiplicative
 // Langmuir variant; the log argument is floored at 1e-6.  Evaluated in FP64:
 // along the channel sigma changes by ~1e-3 of itself per node, so its
-// gradient is a difference that FP32 would resolve only to ~1e-4.
+// gradient is a difference that FP32 would resolve only to ~1e-4.  The
+// surfactant factor ln(1 - psi/psi_inf) varies by O(1) of itself across an
+// interface, so with FP32 / FP16 storage (psi itself carried in FP32) it is
+// formed in FP32, to within the rounding of the psi it is taken of.
 template <typename R>
 __device__ __forceinline__ double sigma_of(const Ctx<R>& c, double T, double psi)
 {
     const double dT = T - c.Trefd;
     double frac = psi * c.ipsid;
     frac = frac > 1.0 - 1e-6 ? 1.0 - 1e-6 : frac;
-    const double L = log(1.0 - frac);
+    const double L = sizeof(R) == 8 ? log(1.0 - frac) : (double)log1pf(-(float)frac);
     if (c.law == 1) return c.s0d + c.s0d * c.betad * (T / c.Trefd) * L + c.sTd * dT + c.sTTd * dT * dT;
     return (c.s0d + c.sTd * dT + c.sTTd * dT * dT) * (1.0 + c.betad * L);
 }

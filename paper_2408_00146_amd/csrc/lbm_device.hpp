@@ -381,14 +381,23 @@ __device__ __forceinline__ R sum9(const R v[9])
 // gradient is a difference that FP32 would resolve only to ~1e-4.  The
 // surfactant factor ln(1 - psi/psi_inf) varies by O(1) of itself across an
 // interface, so with FP32 / FP16 storage (psi itself carried in FP32) it is
-// formed in FP32, to within the rounding of the psi it is taken of.
+// formed in FP32: logf of x = 1 - frac rounded to FP32, plus the first-order
+// term of that rounding, (1 - frac - x) / x (a few ulp of the log over the
+// whole clamped range, where log1pf of an FP32 frac loses digits near 1).
 template <typename R>
 __device__ __forceinline__ double sigma_of(const Ctx<R>& c, double T, double psi)
 {
     const double dT = T - c.Trefd;
     double frac = psi * c.ipsid;
     frac = frac > 1.0 - 1e-6 ? 1.0 - 1e-6 : frac;
-    const double L = sizeof(R) == 8 ? log(1.0 - frac) : (double)log1pf(-(float)frac);
+    double L;
+    if (sizeof(R) == 8) {
+        L = log(1.0 - frac);
+    } else {
+        const double xe = 1.0 - frac;
+        const float x = (float)xe;
+        L = (double)(logf(x) + (float)(xe - (double)x) * __frcp_rn(x));
+    }
     if (c.law == 1) return c.s0d + c.s0d * c.betad * (T / c.Trefd) * L + c.sTd * dT + c.sTTd * dT * dT;
     return (c.s0d + c.sTd * dT + c.sTTd * dT * dT) * (1.0 + c.betad * L);
 }

@@ -332,7 +332,7 @@ __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x,
                     v = dev_b;
                 }
             }
-            buf[(int64_t)(set * 9 + a) * cd.plane + o] = enc<S, R>(R(v), sc);
+            buf[((int64_t)a * cd.plane + o) * 4 + set] = enc<S, R>(R(v), sc);
         }
     }
 }

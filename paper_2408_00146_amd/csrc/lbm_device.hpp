@@ -13,8 +13,10 @@
 //   3. per own node: curvature, CSF force, pressure force, velocity,
 //      pressure, the four central-moment collisions, store into the
 //      destination buffer (pull ping-pong: every node writes only itself).
-// Populations are SoA planes [set][dir][y][pitch] so that a wavefront of 64
-// consecutive x reads/writes contiguous memory.
+// Populations are stored direction-major with the four sets interleaved,
+// [dir][y][pitch][set]: a wavefront of 64 consecutive x reads/writes
+// contiguous memory, and the four sets of one direction of a node are
+// adjacent.
 //
 // Reduced-precision storage (FP32, FP16 x 2^10) keeps each population as a
 // deviation from the rest equilibrium of a per-node reference: for f, q and g
@@ -178,6 +180,75 @@ struct Mem<__half> {
     }
 };
 
+// The four sets of one direction at one node are adjacent in a buffer:
+// ld4 moves all four with one wide load, st2 two adjacent sets (k, k + 1)
+// with one wide store.
+template <typename S>
+struct Vec;
+template <>
+struct Vec<float> {
+    static __device__ __forceinline__ void ld4(Rsrc r, uint32_t v, uint32_t s, float o[4])
+    {
+        // elements are copied out before the bit cast: __builtin_bit_cast of a
+        // vector subscript reads element 0 with this compiler
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
+        const uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
+        o[0] = __builtin_bit_cast(float, w0);
+        o[1] = __builtin_bit_cast(float, w1);
+        o[2] = __builtin_bit_cast(float, w2);
+        o[3] = __builtin_bit_cast(float, w3);
+    }
+    static __device__ __forceinline__ void st2(Rsrc r, uint32_t v, uint32_t s, float a, float b)
+    {
+        decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) q;
+        q[0] = __builtin_bit_cast(uint32_t, a);
+        q[1] = __builtin_bit_cast(uint32_t, b);
+        __builtin_amdgcn_raw_buffer_store_b64(q, r, v, s, 0);
+    }
+};
+template <>
+struct Vec<__half> {
+    static __device__ __forceinline__ void ld4(Rsrc r, uint32_t v, uint32_t s, __half o[4])
+    {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0);
+        o[0] = __ushort_as_half((unsigned short)(q[0] & 0xffffu));
+        o[1] = __ushort_as_half((unsigned short)(q[0] >> 16));
+        o[2] = __ushort_as_half((unsigned short)(q[1] & 0xffffu));
+        o[3] = __ushort_as_half((unsigned short)(q[1] >> 16));
+    }
+    static __device__ __forceinline__ void st2(Rsrc r, uint32_t v, uint32_t s, __half a, __half b)
+    {
+        const uint32_t w = (uint32_t)__half_as_ushort(a) | ((uint32_t)__half_as_ushort(b) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, 0);
+    }
+};
+template <>
+struct Vec<double> {
+    static __device__ __forceinline__ double dbl(uint32_t lo, uint32_t hi)
+    {
+        return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+    }
+    static __device__ __forceinline__ void ld4(Rsrc r, uint32_t v, uint32_t s, double o[4])
+    {
+        const auto q0 = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
+        const auto q1 = __builtin_amdgcn_raw_buffer_load_b128(r, v, s + 16u, 0);
+        o[0] = dbl(q0[0], q0[1]);
+        o[1] = dbl(q0[2], q0[3]);
+        o[2] = dbl(q1[0], q1[1]);
+        o[3] = dbl(q1[2], q1[3]);
+    }
+    static __device__ __forceinline__ void st2(Rsrc r, uint32_t v, uint32_t s, double a, double b)
+    {
+        decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) q;
+        const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+        q[0] = (uint32_t)ua;
+        q[1] = (uint32_t)(ua >> 32);
+        q[2] = (uint32_t)ub;
+        q[3] = (uint32_t)(ub >> 32);
+        __builtin_amdgcn_raw_buffer_store_b128(q, r, v, s, 0);
+    }
+};
+
 // A population buffer as seen by one tile.
 struct View {
     Rsrc r;
@@ -250,16 +321,16 @@ __device__ __forceinline__ S pull_raw(const Ctx<R>& c, View src, int mx, int my,
     constexpr uint32_t E = sizeof(S);
     if (INT) {
         // shift of the source folded into the scalar offset (never negative: plane >= pitch + 1)
-        const uint32_t v = (uint32_t)(my * c.pitch + mx) * E;
-        const uint32_t so = (uint32_t)((SET * 9 + A) * c.plane - EY * c.pitch - EX) * E;
+        const uint32_t v = (uint32_t)(my * c.pitch + mx) * (4u * E);
+        const uint32_t so = (uint32_t)((A * c.plane - EY * c.pitch - EX) * 4 + SET) * E;
         return Mem<S>::ld(src.r, v, so);
     }
     const Link<A> l(nb, mx);
     const int rs = EY > 0 ? nb.rym : (EY < 0 ? nb.ryp : nb.ry0);
     const bool wall = l.wall();
     const uint32_t node = wall ? (uint32_t)(nb.ry0 + mx) : (uint32_t)(rs + l.sx);
-    const uint32_t pln = wall ? (uint32_t)((SET * 9 + opp(A)) * c.plane) : (uint32_t)((SET * 9 + A) * c.plane);
-    return Mem<S>::ld(src.r, (node + pln) * E, 0u);
+    const uint32_t pln = wall ? (uint32_t)(opp(A) * c.plane) : (uint32_t)(A * c.plane);
+    return Mem<S>::ld(src.r, (node + pln) * (4u * E), (uint32_t)SET * E);
 }
 
 template <int SET, int A, bool INT, bool REFS, typename S, typename R, typename RF>
@@ -356,13 +427,72 @@ __device__ __forceinline__ void fix9(const Ctx<R>& c, const S r[9], int ux, int 
     v[8] = pull_fix<SET, 8, INT, REFS, S, R>(c, r[8], ux, uy, mx, base, rf, nb);
 }
 
-// Store the 9 post-collision populations of a set at node offset v (bytes).
-template <int SET, typename S, typename R>
-__device__ __forceinline__ void store9(const Ctx<R>& c, View dst, uint32_t v, const R x[9])
+// Loads of the 36 populations pulled to node (mx, my), one wide load per
+// direction: the four sets of a direction share its source slot (and, beyond
+// a wall, its bounce-back slot).
+template <int A, bool INT, typename S, typename R>
+__device__ __forceinline__ void raw_dir(const Ctx<R>& c, View src, int mx, int my, const Nbr& nb, S* rF, S* rG,
+                                        S* rH, S* rQ)
+{
+    constexpr int EX = ex(A), EY = ey(A);
+    constexpr uint32_t E4 = 4u * sizeof(S);
+    uint32_t v, so;
+    if (INT) {
+        v = (uint32_t)(my * c.pitch + mx) * E4;
+        so = (uint32_t)(A * c.plane - EY * c.pitch - EX) * E4;
+    } else {
+        const Link<A> l(nb, mx);
+        const int rs = EY > 0 ? nb.rym : (EY < 0 ? nb.ryp : nb.ry0);
+        const bool wall = l.wall();
+        const uint32_t node = wall ? (uint32_t)(nb.ry0 + mx) : (uint32_t)(rs + l.sx);
+        const uint32_t pln = wall ? (uint32_t)(opp(A) * c.plane) : (uint32_t)(A * c.plane);
+        v = (node + pln) * E4;
+        so = 0u;
+    }
+    S o[4];
+    Vec<S>::ld4(src.r, v, so, o);
+    rF[A] = o[SET_F];
+    rG[A] = o[SET_G];
+    rH[A] = o[SET_H];
+    rQ[A] = o[SET_Q];
+}
+
+template <bool INT, typename S, typename R>
+__device__ __forceinline__ void raw36(const Ctx<R>& c, View src, int mx, int my, S rF[9], S rG[9], S rH[9], S rQ[9])
+{
+    const Nbr nb = INT ? Nbr{} : nbr_of(c, mx, my);
+    raw_dir<0, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<1, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<2, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<3, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<4, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<5, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<6, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<7, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<8, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+}
+
+// Store the post-collision populations of two adjacent sets (K, K + 1) at
+// node index o, one wide store per direction.
+static_assert(SET_G == SET_F + 1 && SET_Q == SET_H + 1, "paired sets are adjacent");
+template <int K, typename S, typename R>
+__device__ __forceinline__ void store9x2(const Ctx<R>& c, View dst, uint32_t o, const R a[9], const R b[9])
 {
     constexpr uint32_t E = sizeof(S);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Mem<S>::st(enc<S, R>(x[a], c.scale), dst.r, v, (uint32_t)((SET * 9 + a) * c.plane) * E);
+    for (int d = 0; d < 9; ++d)
+        Vec<S>::st2(dst.r, o * (4u * E), (uint32_t)(d * c.plane * 4 + K) * E, enc<S, R>(a[d], c.scale),
+                    enc<S, R>(b[d], c.scale));
+}
+
+// Store the 9 post-collision populations of a set at node index o.
+template <int SET, typename S, typename R>
+__device__ __forceinline__ void store9(const Ctx<R>& c, View dst, uint32_t o, const R x[9])
+{
+    constexpr uint32_t E = sizeof(S);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        Mem<S>::st(enc<S, R>(x[a], c.scale), dst.r, o * (4u * E), (uint32_t)(a * c.plane * 4 + SET) * E);
 }
 
 template <typename R>
@@ -790,18 +920,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         if constexpr (EARLY) {
             // loads, then the references, then the decoding
             S rF[9], rG[9], rH[9], rQ[9], rA[9], rAG[9], rAH[9], rAQ[9], rB[9];
-            if (own_ok) {
-                raw9<SET_F, INT, S, R>(c, src, mx, my, rF);
-                raw9<SET_G, INT, S, R>(c, src, mx, my, rG);
-                raw9<SET_H, INT, S, R>(c, src, mx, my, rH);
-                raw9<SET_Q, INT, S, R>(c, src, mx, my, rQ);
-            }
-            if (a_ok) raw9<SET_F, INT, S, R>(c, src, amx, amy, rA);
-            if (a_ok && a_e1) {
-                raw9<SET_G, INT, S, R>(c, src, amx, amy, rAG);
-                raw9<SET_H, INT, S, R>(c, src, amx, amy, rAH);
-                raw9<SET_Q, INT, S, R>(c, src, amx, amy, rAQ);
-            }
+            if (own_ok) raw36<INT, S, R>(c, src, mx, my, rF, rG, rH, rQ);
+            if (a_ok && a_e1) raw36<INT, S, R>(c, src, amx, amy, rA, rAG, rAH, rAQ);
+            else if (a_ok) raw9<SET_F, INT, S, R>(c, src, amx, amy, rA);
             if (b_ok) raw9<SET_F, INT, S, R>(c, src, bmx, bmy, rB);
             if (REFS) ref_commit();
             // ring slots first (their values die in the sums), the own node last
@@ -841,11 +962,15 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
                 const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
                 R VA[9], VG[9], VH[9], VQ[9], VB[9];
-                if (a_ok) pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
                 if (a_ok && a_e1) {
-                    pull9<SET_G, INT, REFS, S>(c, src, aux, auy, amx, amy, abp, ref_p, VG);
-                    pull9<SET_H, INT, REFS, S>(c, src, aux, auy, amx, amy, abh, no_ref, VH);
-                    pull9<SET_Q, INT, REFS, S>(c, src, aux, auy, amx, amy, abq, ref_q, VQ);
+                    S rA[9], rAG[9], rAH[9], rAQ[9];
+                    raw36<INT, S, R>(c, src, amx, amy, rA, rAG, rAH, rAQ);
+                    fix9<SET_F, INT, REFS, S, R>(c, rA, aux, auy, amx, amy, abf, ref_f, VA);
+                    fix9<SET_G, INT, REFS, S, R>(c, rAG, aux, auy, amx, amy, abp, ref_p, VG);
+                    fix9<SET_H, INT, REFS, S, R>(c, rAH, aux, auy, amx, amy, abh, no_ref, VH);
+                    fix9<SET_Q, INT, REFS, S, R>(c, rAQ, aux, auy, amx, amy, abq, ref_q, VQ);
+                } else if (a_ok) {
+                    pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
                 }
                 const R bbf = ref_f(bux, buy);
                 if (b_ok) pull9<SET_F, INT, REFS, S>(c, src, bux, buy, bmx, bmy, bbf, ref_f, VB);
@@ -858,10 +983,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             if (own_ok) {
-                pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, F);
-                pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, G);
-                pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, H);
-                pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
+                S rF[9], rG[9], rH[9], rQ[9];
+                raw36<INT, S, R>(c, src, mx, my, rF, rG, rH, rQ);
+                fix9<SET_F, INT, REFS, S, R>(c, rF, ux, uy, mx, my, bf, ref_f, F);
+                fix9<SET_G, INT, REFS, S, R>(c, rG, ux, uy, mx, my, bp, ref_p, G);
+                fix9<SET_H, INT, REFS, S, R>(c, rH, ux, uy, mx, my, bh, no_ref, H);
+                fix9<SET_Q, INT, REFS, S, R>(c, rQ, ux, uy, mx, my, bq, ref_q, Q);
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
             }
@@ -1065,18 +1192,15 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             } else {
                 collide_g(gg, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
             }
-            store9<SET_G, S>(c, dst, o * (uint32_t)sizeof(S), gg);
         };
         // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W
         auto do_f = [&](R* f) {
             const R mt = c.Mphi * R(4) * phi * omphi / c.W;
             collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
-            store9<SET_F, S>(c, dst, o * (uint32_t)sizeof(S), f);
         };
         // h: temperature
         auto do_h = [&](R* hh) {
             collide_ad(hh, bh, bh, R(0), R(0), omT, ux, uy);
-            store9<SET_H, S>(c, dst, o * (uint32_t)sizeof(S), hh);
         };
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
         R nbq = R(0);
@@ -1085,26 +1209,33 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
             nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
             collide_ad(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
-            store9<SET_Q, S>(c, dst, o * (uint32_t)sizeof(S), qq);
         };
         if constexpr (OWN1) {
-            // held sets first, g (the largest collision) last: fewer values live at once
-            do_f(F);
+            // held sets in pairs of adjacent sets (h, q), then (f, g), each
+            // pair stored with one wide store per direction; g (the largest
+            // collision) last, so that few values are live at once
             do_h(H);
             do_q(Q);
+            store9x2<SET_H, S>(c, dst, o, H, Q);
+            do_f(F);
             do_g(g);
+            store9x2<SET_F, S>(c, dst, o, F, g);
         } else {
             // each set pulled right before its collision
             do_g(g);
+            store9<SET_G, S>(c, dst, o, g);
             R f[9];
             pull9<SET_F, INT, REFS, S>(c, src, x, y, x, y, phb, ref_f, f);
             do_f(f);
+            store9<SET_F, S>(c, dst, o, f);
             R hh[9];
             pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hh);
             do_h(hh);
+            store9<SET_H, S>(c, dst, o, hh);
             R qq[9];
             pull9<SET_Q, INT, REFS, S>(c, src, x, y, x, y, bq, ref_q, qq);
             do_q(qq);
+            store9<SET_Q, S>(c, dst, o, qq);
         }
         if (REFS) {
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
@@ -1494,7 +1625,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const R p = pstar + R(0.5) * (Fpx * ux + Fpy * uy);
         const R dV = dV_lam(c, phi, omphi);
 
-        const uint32_t o = (uint32_t)(yy * c.pitch + x) * (uint32_t)sizeof(S);
+        const uint32_t o = (uint32_t)(yy * c.pitch + x);
         // the new p* reference is the FP16-rounded p* of this node
         const R nbp = REFS ? R(__half2float(__float2half_rn((float)pstar))) : R(0);
         if (REFS) {

@@ -180,8 +180,7 @@ int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
  * only the scratch half of the ping-pong pair, so the state is unchanged)
  * and keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
  * lbm_tile_shape / lbm_tile_kind describe an index (LBM_E_INVAL if out of
- * range).  A new handle starts with the 64 x 4 tiles (configuration 6),
- * or with configuration 0 (64 x 8) when it mixes FP32 and FP16 storage. */
+ * range).  A new handle starts with the 64 x 4 tiles (configuration 6). */
 int lbm_autotune(lbm_handle* h, int32_t trial_steps);
 int lbm_tile_count(void);
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by);

@@ -25,9 +25,8 @@ struct Shape {
 };
 constexpr Shape kShapes[] = {{64, 8}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}, {64, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-// Initial configuration: 64 x 4 tiles (register-held populations), except
-// for handles that mix FP32 and FP16 storage, whose per-tile branching kernel
-// is faster with 64 x 8 tiles.
+// Initial configuration: 64 x 4 tiles (register-held populations, wide
+// accesses to the four-set records).
 constexpr int kOwnShape = 6;
 static_assert(kShapes[kOwnShape].bx * kShapes[kOwnShape].by == 256, "one node per thread");
 constexpr int kMacroBX = 64, kMacroBY = 8;
@@ -82,9 +81,9 @@ enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
 
 template <int ST, int BX, int BY>
 // Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the 64 x 4
-// FP16-storage and mixed tiles, three (<= 168) for the other FP32/FP16 tiles
-// (the FP32 64 x 4 tile would spill at 128), two for FP64.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 2 : (BX * BY == 256 && ST != ST_F32 ? 4 : 3)))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
+// FP16-storage tiles, three (<= 168) for the other FP32/FP16 and mixed tiles
+// (the FP32 and mixed 64 x 4 tiles would spill at 128), two for FP64.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 2 : (BX * BY == 256 && ST == ST_F16 ? 4 : 3)))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
                                               int ntiles, const int64_t* __restrict__ steps, int t)
 {
     using R = typename std::conditional<ST == ST_F64, double, float>::type;
@@ -823,7 +822,7 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         h->st = any64 ? ST_F64 : (a32 && a16 ? ST_MIXED : (a16 ? ST_F16 : ST_F32));
     }
     h->steps.assign(ncases, 0);
-    h->shape = h->st == ST_MIXED ? 0 : kOwnShape;
+    h->shape = kOwnShape;
 
     size_t o = L.off_pops;
     for (int i = 0; i < ncases; ++i) {

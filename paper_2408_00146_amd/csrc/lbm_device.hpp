@@ -249,6 +249,37 @@ struct Vec<double> {
     }
 };
 
+// The raw (still encoded) populations of the four sets of one direction at
+// one node, as one wide load leaves them; 16-bit values stay packed two per
+// register until they are decoded.  ld1 loads set 0 alone.
+template <typename S>
+struct Raw4 {
+    S v[4];
+    __device__ __forceinline__ void ld(Rsrc r, uint32_t off, uint32_t s) { Vec<S>::ld4(r, off, s, v); }
+    __device__ __forceinline__ void ld1(Rsrc r, uint32_t off, uint32_t s) { v[0] = Mem<S>::ld(r, off, s); }
+    template <int K>
+    __device__ __forceinline__ S get() const { return v[K]; }
+};
+template <>
+struct Raw4<__half> {
+    uint32_t w[2];
+    __device__ __forceinline__ void ld(Rsrc r, uint32_t off, uint32_t s)
+    {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, off, s, 0);
+        w[0] = q[0];
+        w[1] = q[1];
+    }
+    __device__ __forceinline__ void ld1(Rsrc r, uint32_t off, uint32_t s)
+    {
+        w[0] = __builtin_amdgcn_raw_buffer_load_b16(r, off, s, 0);
+    }
+    template <int K>
+    __device__ __forceinline__ __half get() const
+    {
+        return __ushort_as_half((unsigned short)((K & 1) ? (w[K >> 1] >> 16) : (w[K >> 1] & 0xffffu)));
+    }
+};
+
 // A population buffer as seen by one tile.
 struct View {
     Rsrc r;
@@ -427,12 +458,11 @@ __device__ __forceinline__ void fix9(const Ctx<R>& c, const S r[9], int ux, int 
     v[8] = pull_fix<SET, 8, INT, REFS, S, R>(c, r[8], ux, uy, mx, base, rf, nb);
 }
 
-// Loads of the 36 populations pulled to node (mx, my), one wide load per
+// Loads of the populations pulled to node (mx, my), one wide load per
 // direction: the four sets of a direction share its source slot (and, beyond
-// a wall, its bounce-back slot).
-template <int A, bool INT, typename S, typename R>
-__device__ __forceinline__ void raw_dir(const Ctx<R>& c, View src, int mx, int my, const Nbr& nb, S* rF, S* rG,
-                                        S* rH, S* rQ)
+// a wall, its bounce-back slot).  ALL = false loads set f alone.
+template <int A, bool INT, bool ALL, typename S, typename R>
+__device__ __forceinline__ void raw_dir(const Ctx<R>& c, View src, int mx, int my, const Nbr& nb, Raw4<S>* q)
 {
     constexpr int EX = ex(A), EY = ey(A);
     constexpr uint32_t E4 = 4u * sizeof(S);
@@ -449,27 +479,35 @@ __device__ __forceinline__ void raw_dir(const Ctx<R>& c, View src, int mx, int m
         v = (node + pln) * E4;
         so = 0u;
     }
-    S o[4];
-    Vec<S>::ld4(src.r, v, so, o);
-    rF[A] = o[SET_F];
-    rG[A] = o[SET_G];
-    rH[A] = o[SET_H];
-    rQ[A] = o[SET_Q];
+    static_assert(SET_F == 0, "set f is the first of a record");
+    if (ALL) q[A].ld(src.r, v, so);
+    else q[A].ld1(src.r, v, so);
 }
 
-template <bool INT, typename S, typename R>
-__device__ __forceinline__ void raw36(const Ctx<R>& c, View src, int mx, int my, S rF[9], S rG[9], S rH[9], S rQ[9])
+template <bool INT, bool ALL, typename S, typename R>
+__device__ __forceinline__ void raw36(const Ctx<R>& c, View src, int mx, int my, Raw4<S> q[9])
 {
     const Nbr nb = INT ? Nbr{} : nbr_of(c, mx, my);
-    raw_dir<0, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<1, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<2, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<3, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<4, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<5, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<6, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<7, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
-    raw_dir<8, INT, S, R>(c, src, mx, my, nb, rF, rG, rH, rQ);
+    raw_dir<0, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<1, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<2, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<3, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<4, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<5, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<6, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<7, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<8, INT, ALL, S, R>(c, src, mx, my, nb, q);
+}
+
+// fix9 of set SET from the wide-loaded records.
+template <int SET, bool INT, bool REFS, typename S, typename R, typename RF>
+__device__ __forceinline__ void fix9q(const Ctx<R>& c, const Raw4<S> q[9], int ux, int uy, int mx, int my, R base,
+                                      const RF& rf, R v[9])
+{
+    S r[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) r[a] = q[a].template get<SET>();
+    fix9<SET, INT, REFS, S, R>(c, r, ux, uy, mx, my, base, rf, v);
 }
 
 // Store the post-collision populations of two adjacent sets (K, K + 1) at
@@ -771,9 +809,8 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr int NT = 256;
     constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
     // population loads of phase 1a issued before the storage references are
-    // committed (one own node per thread, interior tiles; 16-bit values would
-    // each hold a whole VGPR while in flight, which spills)
-    constexpr bool EARLY = OWN1 && INT && sizeof(S) >= 4;
+    // committed (one own node per thread, interior tiles)
+    constexpr bool EARLY = OWN1 && INT;
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
@@ -919,11 +956,11 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         };
         if constexpr (EARLY) {
             // loads, then the references, then the decoding
-            S rF[9], rG[9], rH[9], rQ[9], rA[9], rAG[9], rAH[9], rAQ[9], rB[9];
-            if (own_ok) raw36<INT, S, R>(c, src, mx, my, rF, rG, rH, rQ);
-            if (a_ok && a_e1) raw36<INT, S, R>(c, src, amx, amy, rA, rAG, rAH, rAQ);
-            else if (a_ok) raw9<SET_F, INT, S, R>(c, src, amx, amy, rA);
-            if (b_ok) raw9<SET_F, INT, S, R>(c, src, bmx, bmy, rB);
+            Raw4<S> qO[9], qA[9], qB[9];
+            if (own_ok) raw36<INT, true, S, R>(c, src, mx, my, qO);
+            if (a_ok && a_e1) raw36<INT, true, S, R>(c, src, amx, amy, qA);
+            else if (a_ok) raw36<INT, false, S, R>(c, src, amx, amy, qA);
+            if (b_ok) raw36<INT, false, S, R>(c, src, bmx, bmy, qB);
             if (REFS) ref_commit();
             // ring slots first (their values die in the sums), the own node last
             {
@@ -931,28 +968,28 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
                 R VA[9], VG[9], VH[9], VQ[9], VB[9];
                 if (a_ok) {
-                    fix9<SET_F, INT, REFS, S, R>(c, rA, aux, auy, amx, amy, abf, ref_f, VA);
+                    fix9q<SET_F, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abf, ref_f, VA);
                     put_f(alx, aly, abf, VA);
                 }
                 if (a_ok && a_e1) {
-                    fix9<SET_G, INT, REFS, S, R>(c, rAG, aux, auy, amx, amy, abp, ref_p, VG);
-                    fix9<SET_H, INT, REFS, S, R>(c, rAH, aux, auy, amx, amy, abh, no_ref, VH);
-                    fix9<SET_Q, INT, REFS, S, R>(c, rAQ, aux, auy, amx, amy, abq, ref_q, VQ);
+                    fix9q<SET_G, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abp, ref_p, VG);
+                    fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, no_ref, VH);
+                    fix9q<SET_Q, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abq, ref_q, VQ);
                     put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
                 }
                 const R bbf = ref_f(bux, buy);
                 if (b_ok) {
-                    fix9<SET_F, INT, REFS, S, R>(c, rB, bux, buy, bmx, bmy, bbf, ref_f, VB);
+                    fix9q<SET_F, INT, REFS, S, R>(c, qB, bux, buy, bmx, bmy, bbf, ref_f, VB);
                     put_f(blx, bly, bbf, VB);
                 }
             }
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             if (own_ok) {
-                fix9<SET_F, INT, REFS, S, R>(c, rF, ux, uy, mx, my, bf, ref_f, F);
-                fix9<SET_G, INT, REFS, S, R>(c, rG, ux, uy, mx, my, bp, ref_p, G);
-                fix9<SET_H, INT, REFS, S, R>(c, rH, ux, uy, mx, my, bh, no_ref, H);
-                fix9<SET_Q, INT, REFS, S, R>(c, rQ, ux, uy, mx, my, bq, ref_q, Q);
+                fix9q<SET_F, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bf, ref_f, F);
+                fix9q<SET_G, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bp, ref_p, G);
+                fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, no_ref, H);
+                fix9q<SET_Q, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bq, ref_q, Q);
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
             }
@@ -963,12 +1000,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
                 R VA[9], VG[9], VH[9], VQ[9], VB[9];
                 if (a_ok && a_e1) {
-                    S rA[9], rAG[9], rAH[9], rAQ[9];
-                    raw36<INT, S, R>(c, src, amx, amy, rA, rAG, rAH, rAQ);
-                    fix9<SET_F, INT, REFS, S, R>(c, rA, aux, auy, amx, amy, abf, ref_f, VA);
-                    fix9<SET_G, INT, REFS, S, R>(c, rAG, aux, auy, amx, amy, abp, ref_p, VG);
-                    fix9<SET_H, INT, REFS, S, R>(c, rAH, aux, auy, amx, amy, abh, no_ref, VH);
-                    fix9<SET_Q, INT, REFS, S, R>(c, rAQ, aux, auy, amx, amy, abq, ref_q, VQ);
+                    Raw4<S> qA[9];
+                    raw36<INT, true, S, R>(c, src, amx, amy, qA);
+                    fix9q<SET_F, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abf, ref_f, VA);
+                    fix9q<SET_G, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abp, ref_p, VG);
+                    fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, no_ref, VH);
+                    fix9q<SET_Q, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abq, ref_q, VQ);
                 } else if (a_ok) {
                     pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
                 }
@@ -983,12 +1020,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
             if (own_ok) {
-                S rF[9], rG[9], rH[9], rQ[9];
-                raw36<INT, S, R>(c, src, mx, my, rF, rG, rH, rQ);
-                fix9<SET_F, INT, REFS, S, R>(c, rF, ux, uy, mx, my, bf, ref_f, F);
-                fix9<SET_G, INT, REFS, S, R>(c, rG, ux, uy, mx, my, bp, ref_p, G);
-                fix9<SET_H, INT, REFS, S, R>(c, rH, ux, uy, mx, my, bh, no_ref, H);
-                fix9<SET_Q, INT, REFS, S, R>(c, rQ, ux, uy, mx, my, bq, ref_q, Q);
+                Raw4<S> qO[9];
+                raw36<INT, true, S, R>(c, src, mx, my, qO);
+                fix9q<SET_F, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bf, ref_f, F);
+                fix9q<SET_G, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bp, ref_p, G);
+                fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, no_ref, H);
+                fix9q<SET_Q, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bq, ref_q, Q);
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
             }

@@ -82,8 +82,9 @@ enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
 template <int ST, int BX, int BY>
 // Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the 64 x 4
 // FP16-storage tiles, three (<= 168) for the other FP32/FP16 and mixed tiles
-// (the FP32 and mixed 64 x 4 tiles would spill at 128), two for FP64.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 2 : (BX * BY == 256 && ST == ST_F16 ? 4 : 3)))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
+// (the FP32 and mixed 64 x 4 tiles would spill at 128) and the FP64 64 x 4
+// tile, two for the larger FP64 tiles.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? (BX * BY == 256 ? 3 : 2) : (BX * BY == 256 && ST == ST_F16 ? 4 : 3)))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
                                               int ntiles, const int64_t* __restrict__ steps, int t)
 {
     using R = typename std::conditional<ST == ST_F64, double, float>::type;

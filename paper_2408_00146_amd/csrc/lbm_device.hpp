@@ -120,6 +120,18 @@ template <>
 __device__ __forceinline__ float dec<float, float>(float v, float) { return v; }
 template <>
 __device__ __forceinline__ float dec<__half, float>(__half v, float inv_scale) { return __half2float(v) * inv_scale; }
+// dec(v) + a; for FP16 one mixed-precision FMA (v * 2^-10 is exact, so the
+// result equals the separate product and sum)
+template <typename S, typename R>
+__device__ __forceinline__ R dec_add(S v, R inv_scale, R a)
+{
+    return dec<S, R>(v, inv_scale) + a;
+}
+template <>
+__device__ __forceinline__ float dec_add<__half, float>(__half v, float inv_scale, float a)
+{
+    return __builtin_fmaf(__half2float(v), inv_scale, a);
+}
 
 template <typename S, typename R>
 __device__ __forceinline__ S enc(R v, R scale);
@@ -182,7 +194,7 @@ struct Mem<__half> {
 
 // The four sets of one direction at one node are adjacent in a buffer:
 // ld4 moves all four with one wide load, st2 two adjacent sets (k, k + 1)
-// with one wide store.
+// with one wide store, st2e the same pair encoded from the compute type.
 template <typename S>
 struct Vec;
 template <>
@@ -205,6 +217,10 @@ struct Vec<float> {
         q[1] = __builtin_bit_cast(uint32_t, b);
         __builtin_amdgcn_raw_buffer_store_b64(q, r, v, s, 0);
     }
+    static __device__ __forceinline__ void st2e(Rsrc r, uint32_t v, uint32_t s, float a, float b, float)
+    {
+        st2(r, v, s, a, b);
+    }
 };
 template <>
 struct Vec<__half> {
@@ -220,6 +236,12 @@ struct Vec<__half> {
     {
         const uint32_t w = (uint32_t)__half_as_ushort(a) | ((uint32_t)__half_as_ushort(b) << 16);
         __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, 0);
+    }
+    // the pair encoded from FP32 (scaled, round to nearest) straight into one word
+    static __device__ __forceinline__ void st2e(Rsrc r, uint32_t v, uint32_t s, float a, float b, float scale)
+    {
+        const __half2 h = __floats2half2_rn(a * scale, b * scale);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, h), r, v, s, 0);
     }
 };
 template <>
@@ -246,6 +268,10 @@ struct Vec<double> {
         q[2] = (uint32_t)ub;
         q[3] = (uint32_t)(ub >> 32);
         __builtin_amdgcn_raw_buffer_store_b128(q, r, v, s, 0);
+    }
+    static __device__ __forceinline__ void st2e(Rsrc r, uint32_t v, uint32_t s, double a, double b, double)
+    {
+        st2(r, v, s, a, b);
     }
 };
 
@@ -371,12 +397,13 @@ __device__ __forceinline__ R pull_fix(const Ctx<R>& c, S raw, int ux, int uy, in
     constexpr int EX = ex(A), EY = ey(A);
     constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q || SET == SET_G);
     const R w = R(wt(A));
-    R val = dec<S, R>(raw, c.inv_scale);
     if (INT) {
-        if (NODE_REF) val += w * (rf(ux - EX, uy - EY) - base);
-        if (REFS && SET == SET_H && EX != 0) val -= w * c.gradT * R(EX);  // linear-law reference of column mx - ex
-        return val;
+        if (NODE_REF) return dec_add<S, R>(raw, c.inv_scale, w * (rf(ux - EX, uy - EY) - base));
+        // linear-law reference of column mx - ex
+        if (REFS && SET == SET_H && EX != 0) return dec_add<S, R>(raw, c.inv_scale, -(w * c.gradT * R(EX)));
+        return dec<S, R>(raw, c.inv_scale);
     }
+    R val = dec<S, R>(raw, c.inv_scale);
     const Link<A> l(nb, mx);
     const bool wall = l.wall();
     constexpr int YS = EY > 0 ? 2 : 3, XS = EX > 0 ? 0 : 1;
@@ -519,8 +546,7 @@ __device__ __forceinline__ void store9x2(const Ctx<R>& c, View dst, uint32_t o, 
     constexpr uint32_t E = sizeof(S);
 #pragma unroll
     for (int d = 0; d < 9; ++d)
-        Vec<S>::st2(dst.r, o * (4u * E), (uint32_t)(d * c.plane * 4 + K) * E, enc<S, R>(a[d], c.scale),
-                    enc<S, R>(b[d], c.scale));
+        Vec<S>::st2e(dst.r, o * (4u * E), (uint32_t)(d * c.plane * 4 + K) * E, a[d], b[d], c.scale);
 }
 
 // Store the 9 post-collision populations of a set at node index o.

@@ -75,8 +75,10 @@ __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int
 }
 
 // Storage selection of a step launch: one storage type per kernel keeps the
-// code of a single tile body in the instruction cache; handles that mix
-// FP32 and FP16 cases use the kernel that branches per tile.
+// code of a single tile body in the instruction cache.  A handle that mixes
+// FP32 and FP16 cases launches the FP16 and the FP32 tile kernels over the two
+// parts of its tile table; the kernel that branches per tile serves the tiles
+// that strip configurations leave to the tile kernel.
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
 
 template <int ST, int BX, int BY>
@@ -446,7 +448,7 @@ int64_t strips_of(const lbm_case& c, int sy) { return strip_ok(c) ? (int64_t)((c
 struct Layout {
     size_t off_cases, off_steps, off_partials, off_diag, off_tiles[kNumShapes], off_strips[kNumStrip], off_rest, off_mtiles,
         off_pops, total;
-    int64_t ntiles[kNumShapes], nstrips[kNumStrip], nrest, nmtiles, max_case_mtiles;
+    int64_t ntiles[kNumShapes], ntiles16[kNumShapes], nstrips[kNumStrip], nrest, nmtiles, max_case_mtiles;
 };
 
 Layout layout_of(const lbm_case* cs, int n)
@@ -470,9 +472,14 @@ Layout layout_of(const lbm_case* cs, int n)
     L.off_diag = o;
     o = align256(o + sizeof(double) * NDIAG_PART);
     for (int s = 0; s < kNumShapes; ++s) {
-        int64_t t = 0;
-        for (int i = 0; i < n; ++i) t += tiles_of(cs[i], kShapes[s].bx, kShapes[s].by);
+        int64_t t = 0, t16 = 0;
+        for (int i = 0; i < n; ++i) {
+            const int64_t k = tiles_of(cs[i], kShapes[s].bx, kShapes[s].by);
+            t += k;
+            if (cs[i].precision == LBM_FP16S) t16 += k;
+        }
         L.ntiles[s] = t;
+        L.ntiles16[s] = t16;
         L.off_tiles[s] = o;
         o = align256(o + sizeof(TileRec) * (size_t)t);
     }
@@ -688,6 +695,17 @@ struct lbm_handle {
         if (shape < kNumShapes) {
             const int64_t nt = L.ntiles[shape];
             if (nt <= 0) return LBM_OK;
+            if (st == ST_MIXED) {
+                // FP16-storage tiles, then the FP32 tiles, each with its own kernel
+                const int64_t n16 = L.ntiles16[shape];
+                hipLaunchKernelGGL(step_kernel(ST_F16, shape), dim3((unsigned)n16), dim3(256), 0, stream, d_cases(),
+                                   d_tiles(shape), (int)n16, d_steps(), t);
+                HIPCHK(hipGetLastError());
+                hipLaunchKernelGGL(step_kernel(ST_F32, shape), dim3((unsigned)(nt - n16)), dim3(256), 0, stream,
+                                   d_cases(), d_tiles(shape) + n16, (int)(nt - n16), d_steps(), t);
+                HIPCHK(hipGetLastError());
+                return LBM_OK;
+            }
             hipLaunchKernelGGL(step_kernel(st, shape), dim3((unsigned)nt), dim3(256), 0, stream, d_cases(),
                                d_tiles(shape), (int)nt, d_steps(), t);
             HIPCHK(hipGetLastError());
@@ -848,7 +866,12 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
     int rc = LBM_OK;
     for (int s = 0; s < kNumShapes && rc == LBM_OK; ++s) {
         tiles.clear();
-        for (int i = 0; i < ncases; ++i) add_tiles(i, kShapes[s].bx, kShapes[s].by);
+        // FP16-storage cases first: a handle that mixes storage types
+        // launches one kernel per storage type over the two parts
+        for (int i = 0; i < ncases; ++i)
+            if (cases[i].precision == LBM_FP16S) add_tiles(i, kShapes[s].bx, kShapes[s].by);
+        for (int i = 0; i < ncases; ++i)
+            if (cases[i].precision != LBM_FP16S) add_tiles(i, kShapes[s].bx, kShapes[s].by);
         rc = upload(h->d_tiles(s));
     }
     for (int j = 0; j < kNumStrip && rc == LBM_OK; ++j) {

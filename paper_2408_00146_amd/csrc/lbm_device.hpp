@@ -56,10 +56,10 @@ struct CaseDev {
     double om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     double Fx, Fy, grav;
     double scale, inv_scale;
-    int64_t plane;      // elements per (set, dir) plane = ny * pitch
+    int64_t plane;      // four-set records per direction plane = ny * pitch + pad
     int64_t max_steps;  // <= 0: unlimited
     uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
-    uint32_t ref_bytes; // bytes of one reference buffer (2 FP16 planes)
+    uint32_t ref_bytes; // bytes of one reference buffer (3 FP16 planes)
     void* buf[2];       // ping-pong population buffers
     __half* rbuf[2];    // per-node references [3 = phi, psi, p*][ny][pitch] of each buffer (refs only)
 };
@@ -870,7 +870,8 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const int ux = x0 - 3 + k % W3, uy = y0 - 3 + k / W3;
             const int mx = wrapx(ux), my = wrapy(uy);
             // ghosts, and beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
-            rok[i] = k < W3 * H3 && !ghostx(ux) && !ghosty(uy) && mx >= 0 && mx < c.nx && my >= 0 && my < c.ny;
+            // (an interior tile's 3-node halo lies inside the lattice)
+            rok[i] = k < W3 * H3 && (INT || (!ghostx(ux) && !ghosty(uy) && mx >= 0 && mx < c.nx && my >= 0 && my < c.ny));
             const uint32_t ob = rok[i] ? (uint32_t)(my * c.pitch + mx) * 2u : 0u;
             ra[i] = Mem<__half>::ld(rsrc, ob, 0);
             rb[i] = Mem<__half>::ld(rsrc, ob, rplane_b);

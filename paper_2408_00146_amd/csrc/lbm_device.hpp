@@ -835,9 +835,10 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr int NT = 256;
     constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
     // population loads of phase 1a issued before the storage references are
-    // committed (one own node per thread, interior tiles; FP64 keeps the
-    // slot-by-slot order, whose fewer values in flight allow three waves)
-    constexpr bool EARLY = OWN1 && INT && sizeof(S) <= 4;
+    // committed (one own node per thread; interior tiles, and with FP16
+    // storage boundary tiles too).  FP64, and FP32 boundary tiles, keep the
+    // slot-by-slot order, whose fewer values in flight keep their wave counts.
+    constexpr bool EARLY = OWN1 && (sizeof(S) == 2 || (INT && sizeof(S) == 4));
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);

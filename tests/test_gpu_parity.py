@@ -224,6 +224,26 @@ def test_fp32_full_size_channel_sampled(env, tile):
     assert max(err.values()) <= 1e-5, err
 
 
+@pytest.mark.parametrize("prec", [cases.FP32, cases.FP16S])
+@pytest.mark.parametrize("variant", ["closed", "periodic"])
+def test_reduced_precision_ragged_64x4(env, prec, variant):
+    """64x4 tiles with FP32 / FP16 storage on a ragged lattice (100x52: partial
+    tiles, boundary tiles on every side), walls all round with Dirichlet T and
+    psi walls, or fully periodic; 30 steps against the oracle (FP32 bar 1e-5;
+    FP16 storage 1e-3 on phi, T, psi and 1e-2 on u)."""
+    lbm, _ = env
+    p = cases.channel(100, 52, 9.0, 4.0, sigma_TT=1e-3, beta_s=0.2, precision=prec)
+    if variant == "closed":
+        p.update(t_bc=[1, 1, 1, 1], psi_bc=[0, 0, 1, 1], psi_w=[0.0, 0.0, 0.2, 0.05])
+    else:
+        p.update(wall=[0, 0, 0, 0], t_bc=[0, 0, 0, 0], psi_bc=[0, 0, 0, 0], gradT=0.0)
+    s, o = run_pair(env, p, 30, tile=(64, 4))
+    bars = {"phi": 1e-5, "u": 1e-5, "T": 1e-5, "psi": 1e-5} if prec == cases.FP32 else \
+        {"phi": 1e-3, "u": 1e-2, "T": 1e-3, "psi": 1e-3}
+    err = compare(s.fields(), o.fields(), tuple(bars))
+    assert all(err[k] <= bars[k] for k in bars), err
+
+
 # ------------------------------------------------------------------ FP16 storage
 
 def test_fp16s_laplace_pressure(env):

@@ -46,10 +46,10 @@ typedef enum {
  * FP32 otherwise (sigma and its gradient are always FP64).  LBM_FP32 and
  * LBM_FP16S store deviations from the rest equilibrium of a per-node
  * reference, X_a - w_a X_ref(x), scaled by 1 (FP32) or 2^10 (FP16): X_ref is
- * the FP16-rounded phi, p* and psi of the node that wrote the value for f, g
- * and q (kept in three FP16 planes next to each population buffer), and the
- * linear wall-temperature law for h.  LBM_FP64 stores the populations
- * themselves.  Every entry point exchanges full FP64 values. */
+ * the FP16-rounded phi, p*, T and psi of the node that wrote the value for f,
+ * g, h and q (kept in four FP16 planes next to each population buffer).
+ * LBM_FP64 stores the populations themselves.  Every entry point exchanges
+ * full FP64 values. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
 
 /* Surface tension equation of state (Sec. 2.1). */

@@ -285,8 +285,7 @@ __device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, 
 // back by y itself through the wall rule of direction abar, so its value is
 // the inverse of that bounce-back / anti-bounce-back.  Reduced-precision
 // storage is relative to the slot node's own references: the FP16-rounded
-// phi, psi and p* of the state at y (written to the reference planes), and
-// the linear wall law for h.
+// phi, psi, p* and T of the state at y (written to the reference planes).
 template <typename S, typename R>
 __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x, int y0y)
 {
@@ -295,20 +294,23 @@ __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x,
     const R sc = R(cd.scale);
     double ref[4] = {0.0, 0.0, 0.0, 0.0};
     if (cd.refs) {
-        double sf = 0.0, sq = 0.0, sg = 0.0;
+        double sf = 0.0, sq = 0.0, sg = 0.0, sh = 0.0;
         for (int a = 0; a < 9; ++a) {
             sf += src_pop(cd, s, SET_F, a, y0x, y0y);
             sq += src_pop(cd, s, SET_Q, a, y0x, y0y);
             sg += src_pop(cd, s, SET_G, a, y0x, y0y);
+            sh += src_pop(cd, s, SET_H, a, y0x, y0y);
         }
-        const __half hf = __float2half_rn((float)sf), hq = __float2half_rn((float)sq), hg = __float2half_rn((float)sg);
+        const __half hf = __float2half_rn((float)sf), hq = __float2half_rn((float)sq), hg = __float2half_rn((float)sg),
+                     ht = __float2half_rn((float)sh);
         cd.rbuf[b][o] = hf;
         cd.rbuf[b][cd.plane + o] = hq;
         cd.rbuf[b][2 * cd.plane + o] = hg;
+        cd.rbuf[b][3 * cd.plane + o] = ht;
         ref[SET_F] = (double)__half2float(hf);
         ref[SET_Q] = (double)__half2float(hq);
         ref[SET_G] = (double)__half2float(hg);
-        ref[SET_H] = cd.T0 + cd.gradT * ((double)y0x - cd.xT0);
+        ref[SET_H] = (double)__half2float(ht);
     }
     for (int set = 0; set < 4; ++set) {
         const double ry = ref[set];
@@ -326,8 +328,7 @@ __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x,
                 const double dev_b = src_pop(cd, s, set, opp(a), y0x, y0y) - w * ry;
                 if (set == SET_H && cd.tbc[side]) {
                     const double Tw = cd.T0 + cd.gradT * ((double)y0x + 0.5 * ex(a) - cd.xT0);
-                    const double d = cd.refs ? 0.5 * cd.gradT * ex(a) : Tw;  // T_w - reference
-                    v = 2.0 * w * d - dev_b;
+                    v = 2.0 * w * (Tw - ry) - dev_b;
                 } else if (set == SET_Q && cd.pbc[side]) {
                     v = 2.0 * w * (cd.psi_w[side] - ry) - dev_b;
                 } else {
@@ -381,10 +382,10 @@ __device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
     auto rf = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[node(ux, uy)])) : R(0); };
     auto rq = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[c.plane + node(ux, uy)])) : R(0); };
     auto rp = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[2 * (int64_t)c.plane + node(ux, uy)])) : R(0); };
-    auto none = [&](int, int) -> R { return R(0); };
+    auto rt = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[3 * (int64_t)c.plane + node(ux, uy)])) : R(0); };
     export_set<SET_F, S>(c, src, x, y, out, n, rf(x, y), rf);
     export_set<SET_G, S>(c, src, x, y, out, n, rp(x, y), rp);
-    export_set<SET_H, S>(c, src, x, y, out, n, REFS ? c.Tlaw(R(x)) : R(0), none);
+    export_set<SET_H, S>(c, src, x, y, out, n, rt(x, y), rt);
     export_set<SET_Q, S>(c, src, x, y, out, n, rq(x, y), rq);
 }
 
@@ -436,8 +437,8 @@ int64_t plane_of(const lbm_case& c) { return (int64_t)c.ny * pitch_of(c.nx) + kP
 
 size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * plane_of(c) * elem_bytes(c.precision)); }
 
-// Per-node storage references (phi, psi, p*) of reduced-precision cases: 3 FP16 planes per buffer.
-size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)3 * plane_of(c) * 2); }
+// Per-node storage references (phi, psi, p*, T) of reduced-precision cases: 4 FP16 planes per buffer.
+size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)4 * plane_of(c) * 2); }
 
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
 

@@ -19,9 +19,9 @@
 // adjacent.
 //
 // Reduced-precision storage (FP32, FP16 x 2^10) keeps each population as a
-// deviation from the rest equilibrium of a per-node reference: for f, q and g
-// the FP16-rounded phi, psi and p* of the node that wrote it (three extra
-// FP16 planes per buffer), for h the linear wall-temperature law.
+// deviation from the rest equilibrium of a per-node reference: for f, q, g
+// and h the FP16-rounded phi, psi, p* and T of the node that wrote it (four
+// extra FP16 planes per buffer).
 // Deviations are O(u, grad) small, so FP16/FP32 keep their relative
 // precision on them; phi and psi are carried as reference + deviation until
 // they enter a difference, so gradients stay accurate where phi is ~1.
@@ -59,9 +59,9 @@ struct CaseDev {
     int64_t plane;      // four-set records per direction plane = ny * pitch + pad
     int64_t max_steps;  // <= 0: unlimited
     uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
-    uint32_t ref_bytes; // bytes of one reference buffer (3 FP16 planes)
+    uint32_t ref_bytes; // bytes of one reference buffer (4 FP16 planes)
     void* buf[2];       // ping-pong population buffers
-    __half* rbuf[2];    // per-node references [3 = phi, psi, p*][ny][pitch] of each buffer (refs only)
+    __half* rbuf[2];    // per-node references [4 = phi, psi, p*, T][plane] of each buffer (refs only)
 };
 
 struct TileRec {
@@ -395,12 +395,10 @@ __device__ __forceinline__ R pull_fix(const Ctx<R>& c, S raw, int ux, int uy, in
                                       const Nbr& nb)
 {
     constexpr int EX = ex(A), EY = ey(A);
-    constexpr bool NODE_REF = REFS && (SET == SET_F || SET == SET_Q || SET == SET_G);
+    constexpr bool NODE_REF = REFS;  // every set has per-node references with reduced-precision storage
     const R w = R(wt(A));
     if (INT) {
         if (NODE_REF) return dec_add<S, R>(raw, c.inv_scale, w * (rf(ux - EX, uy - EY) - base));
-        // linear-law reference of column mx - ex
-        if (REFS && SET == SET_H && EX != 0) return dec_add<S, R>(raw, c.inv_scale, -(w * c.gradT * R(EX)));
         return dec<S, R>(raw, c.inv_scale);
     }
     R val = dec<S, R>(raw, c.inv_scale);
@@ -412,11 +410,9 @@ __device__ __forceinline__ R pull_fix(const Ctx<R>& c, S raw, int ux, int uy, in
         const int rx = wall ? ux : ux - EX, ry = wall ? uy : uy - EY;
         val += w * (rf(rx, ry) - base);
     }
-    // linear-law reference of column sx (not at a wall, where the slot is the node's own)
-    if (REFS && SET == SET_H && EX != 0) val += wall ? R(0) : w * c.gradT * R(l.sx - mx);
     if (SET == SET_H) {
-        // X_w - base; with the linear-law reference exactly -gradT ex / 2
-        const R d = REFS ? R(-0.5) * c.gradT * R(EX) : c.Tlaw(R(mx) - R(0.5) * R(EX)) - base;
+        // T_w at the link midpoint minus the node's reference
+        const R d = R(c.Tlaw_d((double)mx - 0.5 * EX) - (double)base);
         if ((l.wy && c.t_dir(YS)) || (l.wx && c.t_dir(XS))) val = -val + R(2) * w * d;
     }
     if (SET == SET_Q) {
@@ -799,6 +795,7 @@ struct Smem {
     R rf[N3];   // phi reference
     R rq[N3];   // psi reference
     R rp[N3];   // p* reference
+    R rt[N3];   // T reference
     R phd[W2 * H2];
     R phb[N2B];
     double sg[W1 * H1];  // sigma (FP64)
@@ -848,7 +845,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
     auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
     auto ref_p = [&](int ux, int uy) -> R { return REFS ? sh.rp[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
-    auto no_ref = [&](int, int) -> R { return R(0); };
+    auto ref_t = [&](int ux, int uy) -> R { return REFS ? sh.rt[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
+    // T - T_w(ux) of a slot from its reference and the sum of its h deviations
+    auto t_dev = [&](int ux, R bt, R sum) -> R { return R((double)bt - c.Tlaw_d((double)ux)) + sum; };
     // lattice node of an unwrapped coordinate on a periodic axis
     auto wrapx = [&](int u) { return INT || c.wallx ? u : (u < 0 ? u + c.nx : (u >= c.nx ? u - c.nx : u)); };
     auto wrapy = [&](int u) { return INT || c.wally ? u : (u < 0 ? u + c.ny : (u >= c.ny ? u - c.ny : u)); };
@@ -862,7 +861,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     // node per thread the population loads of phase 1a are issued before the
     // references are committed to LDS.
     constexpr int NI = REFS ? (W3 * H3 + NT - 1) / NT : 1;
-    __half ra[NI], rb[NI], rd[NI];
+    __half ra[NI], rb[NI], rd[NI], re[NI];
     bool rok[NI];
     auto ref_issue = [&]() {
 #pragma unroll
@@ -877,6 +876,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             ra[i] = Mem<__half>::ld(rsrc, ob, 0);
             rb[i] = Mem<__half>::ld(rsrc, ob, rplane_b);
             rd[i] = Mem<__half>::ld(rsrc, ob, 2u * rplane_b);
+            re[i] = Mem<__half>::ld(rsrc, ob, 3u * rplane_b);
         }
     };
     auto ref_commit = [&]() {
@@ -887,6 +887,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 sh.rf[k] = rok[i] ? R(__half2float(ra[i])) : R(0);
                 sh.rq[k] = rok[i] ? R(__half2float(rb[i])) : R(0);
                 sh.rp[k] = rok[i] ? R(__half2float(rd[i])) : R(0);
+                sh.rt[k] = rok[i] ? R(__half2float(re[i])) : R(0);
             }
         }
         __syncthreads();
@@ -915,10 +916,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, v);
             sh.ps[e1] = sum9(v);
             if (REFS) sh.psb[e1] = bp;
-            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
-            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, v);
-            // T - T_w(ux): with the linear-law reference exactly gradT (mx - ux) + sum
-            sh.ts[e1] = REFS ? c.gradT * R(mx - ux) + sum9(v) : R((double)sum9(v) - c.Tlaw_d((double)ux));
+            const R bh = ref_t(ux, uy);
+            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, ref_t, v);
+            sh.ts[e1] = t_dev(ux, bh, sum9(v));
             const R bq = ref_q(ux, uy);
             pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, v);
             sh.pq[e1] = bq + sum9(v);
@@ -975,12 +975,11 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             sh.phd[k] = sum9(v);
             if (REFS) sh.phb[k] = base;
         };
-        auto put_ghq = [&](int lx, int ly, int sux, int smx, R pb, R qb, const R* vg, const R* vh, const R* vq) {
+        auto put_ghq = [&](int lx, int ly, int sux, R pb, R hb, R qb, const R* vg, const R* vh, const R* vq) {
             const int e1 = (ly - 1) * W1 + (lx - 1);
             sh.ps[e1] = sum9(vg);
             if (REFS) sh.psb[e1] = pb;
-            // T - T_w(ux): with the linear-law reference exactly gradT (mx - ux) + sum
-            sh.ts[e1] = REFS ? c.gradT * R(smx - sux) + sum9(vh) : R((double)sum9(vh) - c.Tlaw_d((double)sux));
+            sh.ts[e1] = t_dev(sux, hb, sum9(vh));
             sh.pq[e1] = qb + sum9(vq);
         };
         if constexpr (EARLY) {
@@ -994,7 +993,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             // ring slots first (their values die in the sums), the own node last
             {
                 const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
-                const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
+                const R abh = ref_t(aux, auy);
                 R VA[9], VG[9], VH[9], VQ[9], VB[9];
                 if (a_ok) {
                     fix9q<SET_F, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abf, ref_f, VA);
@@ -1002,9 +1001,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 }
                 if (a_ok && a_e1) {
                     fix9q<SET_G, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abp, ref_p, VG);
-                    fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, no_ref, VH);
+                    fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, ref_t, VH);
                     fix9q<SET_Q, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abq, ref_q, VQ);
-                    put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
+                    put_ghq(alx, aly, aux, abp, abh, abq, VG, VH, VQ);
                 }
                 const R bbf = ref_f(bux, buy);
                 if (b_ok) {
@@ -1013,27 +1012,27 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 }
             }
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
-            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+            const R bh = ref_t(ux, uy);
             if (own_ok) {
                 fix9q<SET_F, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bf, ref_f, F);
                 fix9q<SET_G, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bp, ref_p, G);
-                fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, no_ref, H);
+                fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, ref_t, H);
                 fix9q<SET_Q, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bq, ref_q, Q);
                 put_f(olx, oly, bf, F);
-                put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
+                put_ghq(olx, oly, ux, bp, bh, bq, G, H, Q);
             }
         } else {
             // ring slots first, then the own node (fewer values live at once)
             {
                 const R abf = ref_f(aux, auy), abp = ref_p(aux, auy), abq = ref_q(aux, auy);
-                const R abh = REFS ? c.Tlaw(R(amx)) : R(0);
+                const R abh = ref_t(aux, auy);
                 R VA[9], VG[9], VH[9], VQ[9], VB[9];
                 if (a_ok && a_e1) {
                     Raw4<S> qA[9];
                     raw36<INT, true, S, R>(c, src, amx, amy, qA);
                     fix9q<SET_F, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abf, ref_f, VA);
                     fix9q<SET_G, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abp, ref_p, VG);
-                    fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, no_ref, VH);
+                    fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, ref_t, VH);
                     fix9q<SET_Q, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abq, ref_q, VQ);
                 } else if (a_ok) {
                     pull9<SET_F, INT, REFS, S>(c, src, aux, auy, amx, amy, abf, ref_f, VA);
@@ -1042,21 +1041,21 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 if (b_ok) pull9<SET_F, INT, REFS, S>(c, src, bux, buy, bmx, bmy, bbf, ref_f, VB);
                 if (a_ok) {
                     put_f(alx, aly, abf, VA);
-                    if (a_e1) put_ghq(alx, aly, aux, amx, abp, abq, VG, VH, VQ);
+                    if (a_e1) put_ghq(alx, aly, aux, abp, abh, abq, VG, VH, VQ);
                 }
                 if (b_ok) put_f(blx, bly, bbf, VB);
             }
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
-            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+            const R bh = ref_t(ux, uy);
             if (own_ok) {
                 Raw4<S> qO[9];
                 raw36<INT, true, S, R>(c, src, mx, my, qO);
                 fix9q<SET_F, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bf, ref_f, F);
                 fix9q<SET_G, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bp, ref_p, G);
-                fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, no_ref, H);
+                fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, ref_t, H);
                 fix9q<SET_Q, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bq, ref_q, Q);
                 put_f(olx, oly, bf, F);
-                put_ghq(olx, oly, ux, mx, bp, bq, G, H, Q);
+                put_ghq(olx, oly, ux, bp, bh, bq, G, H, Q);
             }
         }
     } else {
@@ -1204,12 +1203,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         const R uy = (jy + R(0.5) * cs2 * Fty) / (rho * cs2);
         const R p = pstar + R(0.5) * (Fpx * ux + Fpy * uy);
         const R dV = dV_lam(c, phi, omphi);
-        const R bh = REFS ? c.Tlaw(R(x)) : R(0);
+        const R bh = ref_t(x, y);
         const R bq = ref_q(x, y);
 
         if (MODE == MODE_MACRO) {
             R hv[9], qv[9], fv[9];
-            pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hv);
+            pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, ref_t, hv);
             pull9<SET_Q, INT, REFS, S>(c, src, x, y, x, y, bq, ref_q, qv);
             pull9<SET_F, INT, REFS, S>(c, src, x, y, x, y, phb, ref_f, fv);
             const R T = bh + sum9(hv);
@@ -1264,9 +1263,11 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R mt = c.Mphi * R(4) * phi * omphi / c.W;
             collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
         };
-        // h: temperature
+        // h: temperature; the new storage reference is the FP16-rounded T of this node
+        R nbt = R(0);
         auto do_h = [&](R* hh) {
-            collide_ad(hh, bh, bh, R(0), R(0), omT, ux, uy);
+            nbt = REFS ? R(__half2float(__float2half_rn((float)(bh + sum9(hh))))) : R(0);
+            collide_ad(hh, bh, nbt, R(0), R(0), omT, ux, uy);
         };
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
         R nbq = R(0);
@@ -1295,7 +1296,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             do_f(f);
             store9<SET_F, S>(c, dst, o, f);
             R hh[9];
-            pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, no_ref, hh);
+            pull9<SET_H, INT, REFS, S>(c, src, x, y, x, y, bh, ref_t, hh);
             do_h(hh);
             store9<SET_H, S>(c, dst, o, hh);
             R qq[9];
@@ -1307,6 +1308,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
             Mem<__half>::st(__float2half_rn((float)nbq), rdst, o * 2u, rplane_b);
             Mem<__half>::st(__float2half_rn((float)nbp), rdst, o * 2u, 2u * rplane_b);
+            Mem<__half>::st(__float2half_rn((float)nbt), rdst, o * 2u, 3u * rplane_b);
         }
     }
 }
@@ -1347,6 +1349,7 @@ struct StripSmem {
     R rf[REFS ? RING * W3 : 1];  // phi reference
     R rq[REFS ? RING * W3 : 1];  // psi reference
     R rp[REFS ? RING * W3 : 1];  // p* reference
+    R rt[REFS ? RING * W3 : 1];  // T reference
     R phd[RING * W2];            // phi deviation from its reference
     R phb[REFS ? RING * W2 : 1];
     double sg[RING1 * W1];       // sigma (FP64)
@@ -1396,7 +1399,9 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
     auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[i3(ux, uy)] : R(0); };
     auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[i3(ux, uy)] : R(0); };
     auto ref_p = [&](int ux, int uy) -> R { return REFS ? sh.rp[i3(ux, uy)] : R(0); };
-    auto no_ref = [&](int, int) -> R { return R(0); };
+    auto ref_t = [&](int ux, int uy) -> R { return REFS ? sh.rt[i3(ux, uy)] : R(0); };
+    // T - T_w(ux) of a node from its reference and the sum of its h deviations
+    auto t_dev = [&](int ux, R bt, R sum) -> R { return R((double)bt - c.Tlaw_d((double)ux)) + sum; };
     // lattice node of an unwrapped coordinate (overhangs are shorter than the lattice)
     auto wrapx = [&](int v) { return c.wallx ? v : (v < 0 ? v + c.nx : (v >= c.nx ? v - c.nx : v)); };
     auto wrapy = [&](int v) { return c.wally ? v : (v < 0 ? v + c.ny : (v >= c.ny ? v - c.ny : v)); };
@@ -1411,27 +1416,30 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const int n = (rb - ra + 1) * W3;
         for (int k = tid; k < n; k += NT) {
             const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
-            R a = R(0), b = R(0), d = R(0);
+            R a = R(0), b = R(0), d = R(0), t = R(0);
             if (!ghostx(ux) && !ghosty(uy)) {
                 const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
                 a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
                 b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
                 d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
+                t = R(__half2float(Mem<__half>::ld(rsrc, ob, 3u * rplane_b)));
             }
             const int e = i3(ux, uy);
             sh.rf[e] = a;
             sh.rq[e] = b;
             sh.rp[e] = d;
+            sh.rt[e] = t;
         }
     };
 
     // the same for the next iteration's rows, split into issue and commit so
     // that the loads are in flight during the normals (at most 2 slots per thread)
     static_assert(BY * W3 <= 2 * NT, "reference prefetch holds two slots per thread");
-    auto ref_fetch = [&](int ra, int k, R& a, R& b, R& d) {
+    auto ref_fetch = [&](int ra, int k, R& a, R& b, R& d, R& t) {
         a = R(0);
         b = R(0);
         d = R(0);
+        t = R(0);
         if (!REFS || k >= BY * W3) return;
         const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
         if (!ghostx(ux) && !ghosty(uy)) {
@@ -1439,14 +1447,16 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
             b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
             d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
+            t = R(__half2float(Mem<__half>::ld(rsrc, ob, 3u * rplane_b)));
         }
     };
-    auto ref_put = [&](int ra, int k, R a, R b, R d) {
+    auto ref_put = [&](int ra, int k, R a, R b, R d, R t) {
         if (!REFS || k >= BY * W3) return;
         const int e = i3(x0 - 3 + k % W3, ra + k / W3);
         sh.rf[e] = a;
         sh.rq[e] = b;
         sh.rp[e] = d;
+        sh.rt[e] = t;
     };
 
     // p*, T, psi of the node at unwrapped (ux, uy) into the rings (ghosts: zeros)
@@ -1460,9 +1470,9 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         if (!gh) {
             pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, v);
             pv = sum9(v);
-            const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
-            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, v);
-            tv = REFS ? c.gradT * R(mx - ux) + sum9(v) : R((double)sum9(v) - c.Tlaw_d((double)ux));
+            const R bh = ref_t(ux, uy);
+            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, ref_t, v);
+            tv = t_dev(ux, bh, sum9(v));
             const R bq = ref_q(ux, uy);
             pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, v);
             qv = bq + sum9(v);
@@ -1501,11 +1511,11 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const bool gh = !INT && (ghostx(ux) || ghosty(uy));
         const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
         const R bf = ref_f(ux, uy), bq = ref_q(ux, uy), bp = ref_p(ux, uy);
-        const R bh = REFS ? c.Tlaw(R(mx)) : R(0);
+        const R bh = ref_t(ux, uy);
         if (!gh) {
             pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, F);
             pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, G);
-            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, no_ref, H);
+            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, ref_t, H);
             pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
         } else {
 #pragma unroll
@@ -1520,7 +1530,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             const int e = i1(ux, uy);
             sh.ps[e] = gh ? R(0) : sum9(G);
             if (REFS) sh.psb[e] = gh ? R(0) : bp;
-            sh.ts[e] = gh ? R(0) : (REFS ? c.gradT * R(mx - ux) + sum9(H) : R((double)sum9(H) - c.Tlaw_d((double)ux)));
+            sh.ts[e] = gh ? R(0) : t_dev(ux, bh, sum9(H));
             sh.pq[e] = gh ? R(0) : bq + sum9(Q);
         }
     };
@@ -1679,7 +1689,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         const R Ftx = Fsx + c.Fx;
         const R Fty = Fsy + c.Fy - (rho - c.rhoA) * c.grav;
 
-        const R bh = REFS ? c.Tlaw(R(x)) : R(0);
+        const R bh = ref_t(x, yy);
         const R bq = ref_q(x, yy);
         // live nodes are lattice nodes: x, yy need no wrap
         if (!REG) pull9<SET_G, INT, REFS, S>(c, src, x, yy, x, yy, pbase, ref_p, G);
@@ -1709,8 +1719,9 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         collide_ad(F, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
         store9<SET_F, S>(c, dst, o, F);
         // h: temperature
-        if (!REG) pull9<SET_H, INT, REFS, S>(c, src, x, yy, x, yy, bh, no_ref, H);
-        collide_ad(H, bh, bh, R(0), R(0), omT, ux, uy);
+        if (!REG) pull9<SET_H, INT, REFS, S>(c, src, x, yy, x, yy, bh, ref_t, H);
+        const R nbt = REFS ? R(__half2float(__float2half_rn((float)(bh + sum9(H))))) : R(0);
+        collide_ad(H, bh, nbt, R(0), R(0), omT, ux, uy);
         store9<SET_H, S>(c, dst, o, H);
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
         if (!REG) pull9<SET_Q, INT, REFS, S>(c, src, x, yy, x, yy, bq, ref_q, Q);
@@ -1724,6 +1735,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             Mem<__half>::st(__float2half_rn((float)nbf), rdst, oh, 0);
             Mem<__half>::st(__float2half_rn((float)nbq), rdst, oh, rplane_b);
             Mem<__half>::st(__float2half_rn((float)nbp), rdst, oh, 2u * rplane_b);
+            Mem<__half>::st(__float2half_rn((float)nbt), rdst, oh, 3u * rplane_b);
         }
     };
 
@@ -1766,15 +1778,15 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             __syncthreads();
         }
         const bool more = y + BY < y1;
-        R ra0, rb0, rd0, ra1, rb1, rd1;
+        R ra0, rb0, rd0, rt0, ra1, rb1, rd1, rt1;
         if (more) {
-            ref_fetch(y + BY + 3, tid, ra0, rb0, rd0);
-            ref_fetch(y + BY + 3, tid + NT, ra1, rb1, rd1);
+            ref_fetch(y + BY + 3, tid, ra0, rb0, rd0, rt0);
+            ref_fetch(y + BY + 3, tid + NT, ra1, rb1, rd1, rt1);
         }
         normals(y + 1, y + BY);
         if (more) {
-            ref_put(y + BY + 3, tid, ra0, rb0, rd0);
-            ref_put(y + BY + 3, tid + NT, ra1, rb1, rd1);
+            ref_put(y + BY + 3, tid, ra0, rb0, rd0, rt0);
+            ref_put(y + BY + 3, tid + NT, ra1, rb1, rd1, rt1);
         }
         __syncthreads();
         if (REG || !it) collide_row(BoolC<false>{}, y);

@@ -303,10 +303,10 @@ __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x,
         }
         const __half hf = __float2half_rn((float)sf), hq = __float2half_rn((float)sq), hg = __float2half_rn((float)sg),
                      ht = __float2half_rn((float)sh);
-        cd.rbuf[b][o] = hf;
-        cd.rbuf[b][cd.plane + o] = hq;
-        cd.rbuf[b][2 * cd.plane + o] = hg;
-        cd.rbuf[b][3 * cd.plane + o] = ht;
+        cd.rbuf[b][4 * o + 0] = hf;
+        cd.rbuf[b][4 * o + 1] = hq;
+        cd.rbuf[b][4 * o + 2] = hg;
+        cd.rbuf[b][4 * o + 3] = ht;
         ref[SET_F] = (double)__half2float(hf);
         ref[SET_Q] = (double)__half2float(hq);
         ref[SET_G] = (double)__half2float(hg);
@@ -379,10 +379,10 @@ __device__ void export_node(const CaseDev& cd, int b, int x, int y, double* out)
         if (!c.wally) uy = uy < 0 ? uy + c.ny : (uy >= c.ny ? uy - c.ny : uy);
         return (int64_t)uy * c.pitch + ux;
     };
-    auto rf = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[node(ux, uy)])) : R(0); };
-    auto rq = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[c.plane + node(ux, uy)])) : R(0); };
-    auto rp = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[2 * (int64_t)c.plane + node(ux, uy)])) : R(0); };
-    auto rt = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[3 * (int64_t)c.plane + node(ux, uy)])) : R(0); };
+    auto rf = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[4 * node(ux, uy) + 0])) : R(0); };
+    auto rq = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[4 * node(ux, uy) + 1])) : R(0); };
+    auto rp = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[4 * node(ux, uy) + 2])) : R(0); };
+    auto rt = [&](int ux, int uy) -> R { return REFS ? R(__half2float(rb[4 * node(ux, uy) + 3])) : R(0); };
     export_set<SET_F, S>(c, src, x, y, out, n, rf(x, y), rf);
     export_set<SET_G, S>(c, src, x, y, out, n, rp(x, y), rp);
     export_set<SET_H, S>(c, src, x, y, out, n, rt(x, y), rt);
@@ -437,7 +437,7 @@ int64_t plane_of(const lbm_case& c) { return (int64_t)c.ny * pitch_of(c.nx) + kP
 
 size_t case_pop_bytes(const lbm_case& c) { return align256((size_t)36 * plane_of(c) * elem_bytes(c.precision)); }
 
-// Per-node storage references (phi, psi, p*, T) of reduced-precision cases: 4 FP16 planes per buffer.
+// Per-node storage references (phi, psi, p*, T) of reduced-precision cases: one 8-byte record per node.
 size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : align256((size_t)4 * plane_of(c) * 2); }
 
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }

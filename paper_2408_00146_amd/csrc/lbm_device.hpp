@@ -20,8 +20,8 @@
 //
 // Reduced-precision storage (FP32, FP16 x 2^10) keeps each population as a
 // deviation from the rest equilibrium of a per-node reference: for f, q, g
-// and h the FP16-rounded phi, psi, p* and T of the node that wrote it (four
-// extra FP16 planes per buffer).
+// and h the FP16-rounded phi, psi, p* and T of the node that wrote it (one
+// 8-byte record of four FP16 values per node, next to each buffer).
 // Deviations are O(u, grad) small, so FP16/FP32 keep their relative
 // precision on them; phi and psi are carried as reference + deviation until
 // they enter a difference, so gradients stay accurate where phi is ~1.
@@ -59,9 +59,9 @@ struct CaseDev {
     int64_t plane;      // four-set records per direction plane = ny * pitch + pad
     int64_t max_steps;  // <= 0: unlimited
     uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
-    uint32_t ref_bytes; // bytes of one reference buffer (4 FP16 planes)
+    uint32_t ref_bytes; // bytes of one reference buffer (4 FP16 values per node)
     void* buf[2];       // ping-pong population buffers
-    __half* rbuf[2];    // per-node references [4 = phi, psi, p*, T][plane] of each buffer (refs only)
+    __half* rbuf[2];    // per-node references [plane][4 = phi, psi, p*, T] of each buffer (refs only)
 };
 
 struct TileRec {
@@ -305,6 +305,29 @@ struct Raw4<__half> {
         return __ushort_as_half((unsigned short)((K & 1) ? (w[K >> 1] >> 16) : (w[K >> 1] & 0xffffu)));
     }
 };
+
+// The four storage references of a node (phi, psi, p*, T, FP16 each) form one
+// 8-byte record, read and written with one access.
+__device__ __forceinline__ void ref_ld(Rsrc r, uint32_t node, uint32_t& lo, uint32_t& hi)
+{
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, node * 8u, 0, 0);
+    lo = w[0];
+    hi = w[1];
+}
+template <int K>
+__device__ __forceinline__ float ref_get(uint32_t lo, uint32_t hi)
+{
+    const uint32_t w = K < 2 ? lo : hi;
+    return __half2float(__ushort_as_half((unsigned short)((K & 1) ? (w >> 16) : (w & 0xffffu))));
+}
+// values already FP16-exact (the rounded moments), so the conversion is exact
+__device__ __forceinline__ void ref_st(Rsrc r, uint32_t node, float f, float q, float p, float t)
+{
+    decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) w;
+    w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f, q));
+    w[1] = __builtin_bit_cast(uint32_t, __floats2half2_rn(p, t));
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, node * 8u, 0, 0);
+}
 
 // A population buffer as seen by one tile.
 struct View {
@@ -839,7 +862,6 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
-    const uint32_t rplane_b = (uint32_t)c.plane * 2u;  // reference planes share the population pitch
 
     // per-node references of the f and q sets at unwrapped tile coordinates
     auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
@@ -861,7 +883,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     // node per thread the population loads of phase 1a are issued before the
     // references are committed to LDS.
     constexpr int NI = REFS ? (W3 * H3 + NT - 1) / NT : 1;
-    __half ra[NI], rb[NI], rd[NI], re[NI];
+    uint32_t rlo[NI], rhi[NI];
     bool rok[NI];
     auto ref_issue = [&]() {
 #pragma unroll
@@ -872,11 +894,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             // ghosts, and beyond one wrap (tiny periodic lattice, far ragged halo): no live node reads it
             // (an interior tile's 3-node halo lies inside the lattice)
             rok[i] = k < W3 * H3 && (INT || (!ghostx(ux) && !ghosty(uy) && mx >= 0 && mx < c.nx && my >= 0 && my < c.ny));
-            const uint32_t ob = rok[i] ? (uint32_t)(my * c.pitch + mx) * 2u : 0u;
-            ra[i] = Mem<__half>::ld(rsrc, ob, 0);
-            rb[i] = Mem<__half>::ld(rsrc, ob, rplane_b);
-            rd[i] = Mem<__half>::ld(rsrc, ob, 2u * rplane_b);
-            re[i] = Mem<__half>::ld(rsrc, ob, 3u * rplane_b);
+            ref_ld(rsrc, rok[i] ? (uint32_t)(my * c.pitch + mx) : 0u, rlo[i], rhi[i]);
         }
     };
     auto ref_commit = [&]() {
@@ -884,10 +902,10 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         for (int i = 0; i < NI; ++i) {
             const int k = tid + i * NT;
             if (k < W3 * H3) {
-                sh.rf[k] = rok[i] ? R(__half2float(ra[i])) : R(0);
-                sh.rq[k] = rok[i] ? R(__half2float(rb[i])) : R(0);
-                sh.rp[k] = rok[i] ? R(__half2float(rd[i])) : R(0);
-                sh.rt[k] = rok[i] ? R(__half2float(re[i])) : R(0);
+                sh.rf[k] = rok[i] ? R(ref_get<0>(rlo[i], rhi[i])) : R(0);
+                sh.rq[k] = rok[i] ? R(ref_get<1>(rlo[i], rhi[i])) : R(0);
+                sh.rp[k] = rok[i] ? R(ref_get<2>(rlo[i], rhi[i])) : R(0);
+                sh.rt[k] = rok[i] ? R(ref_get<3>(rlo[i], rhi[i])) : R(0);
             }
         }
         __syncthreads();
@@ -1305,10 +1323,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             store9<SET_Q, S>(c, dst, o, qq);
         }
         if (REFS) {
-            Mem<__half>::st(__float2half_rn((float)nbf), rdst, o * 2u, 0);
-            Mem<__half>::st(__float2half_rn((float)nbq), rdst, o * 2u, rplane_b);
-            Mem<__half>::st(__float2half_rn((float)nbp), rdst, o * 2u, 2u * rplane_b);
-            Mem<__half>::st(__float2half_rn((float)nbt), rdst, o * 2u, 3u * rplane_b);
+            ref_st(rdst, o, (float)nbf, (float)nbq, (float)nbp, (float)nbt);
         }
     }
 }
@@ -1391,7 +1406,6 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
     int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int x0 = u.x0, y0 = u.y0, y1 = u.y1;
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
-    const uint32_t rplane_b = (uint32_t)c.plane * 2u;
 
     auto i3 = [&](int ux, int uy) { return (uy & M) * W3 + (ux - x0 + 3); };
     auto i2 = [&](int ux, int uy) { return (uy & M) * W2 + (ux - x0 + 2); };
@@ -1418,11 +1432,12 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
             const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
             R a = R(0), b = R(0), d = R(0), t = R(0);
             if (!ghostx(ux) && !ghosty(uy)) {
-                const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
-                a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
-                b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
-                d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
-                t = R(__half2float(Mem<__half>::ld(rsrc, ob, 3u * rplane_b)));
+                uint32_t lo, hi;
+                ref_ld(rsrc, (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)), lo, hi);
+                a = R(ref_get<0>(lo, hi));
+                b = R(ref_get<1>(lo, hi));
+                d = R(ref_get<2>(lo, hi));
+                t = R(ref_get<3>(lo, hi));
             }
             const int e = i3(ux, uy);
             sh.rf[e] = a;
@@ -1443,11 +1458,12 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         if (!REFS || k >= BY * W3) return;
         const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
         if (!ghostx(ux) && !ghosty(uy)) {
-            const uint32_t ob = (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)) * 2u;
-            a = R(__half2float(Mem<__half>::ld(rsrc, ob, 0)));
-            b = R(__half2float(Mem<__half>::ld(rsrc, ob, rplane_b)));
-            d = R(__half2float(Mem<__half>::ld(rsrc, ob, 2u * rplane_b)));
-            t = R(__half2float(Mem<__half>::ld(rsrc, ob, 3u * rplane_b)));
+            uint32_t lo, hi;
+            ref_ld(rsrc, (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)), lo, hi);
+            a = R(ref_get<0>(lo, hi));
+            b = R(ref_get<1>(lo, hi));
+            d = R(ref_get<2>(lo, hi));
+            t = R(ref_get<3>(lo, hi));
         }
     };
     auto ref_put = [&](int ra, int k, R a, R b, R d, R t) {
@@ -1731,11 +1747,7 @@ __device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, V
         collide_ad(Q, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
         store9<SET_Q, S>(c, dst, o, Q);
         if (REFS) {
-            const uint32_t oh = (uint32_t)(yy * c.pitch + x) * 2u;
-            Mem<__half>::st(__float2half_rn((float)nbf), rdst, oh, 0);
-            Mem<__half>::st(__float2half_rn((float)nbq), rdst, oh, rplane_b);
-            Mem<__half>::st(__float2half_rn((float)nbp), rdst, oh, 2u * rplane_b);
-            Mem<__half>::st(__float2half_rn((float)nbt), rdst, oh, 3u * rplane_b);
+            ref_st(rdst, o, (float)nbf, (float)nbq, (float)nbp, (float)nbt);
         }
     };
 

@@ -264,6 +264,29 @@ def test_fp16s_centroid(env, tile):
     assert abs(dg["xc"] - do["xc"]) <= 0.05 and abs(dg["yc"] - do["yc"]) <= 0.05
 
 
+def test_long_run_reduced_precision(env):
+    """10000 steps of a 128x64 migrating-bubble channel with FP32 and FP16
+    storage against the oracle: FP32 within 1e-5 on phi, u, T, psi; FP16
+    storage centroid within 0.05 lu, Laplace pressure jump within 1 %, T
+    within 1e-3 (the per-node T reference keeps the h deviations small where
+    T departs from the wall law, at the adiabatic channel ends)."""
+    lbm, O = env
+    p = cases.channel(128, 64, 10.0, 4.0, sigma_TT=1e-3, beta_s=0.2)
+    o = O.Oracle(p)
+    o.step(10000)
+    do, of = o.diag(), o.fields()
+    s32 = lbm.Solver(dict(p, precision=cases.FP32))
+    s32.step(10000)
+    err = compare(s32.fields(), of, ("phi", "u", "T", "psi"))
+    assert max(err.values()) <= 1e-5, err
+    s16 = lbm.Solver(dict(p, precision=cases.FP16S))
+    s16.step(10000)
+    dg = s16.reduce()
+    assert abs(dg["xc"] - do["xc"]) <= 0.05 and abs(dg["yc"] - do["yc"]) <= 0.05
+    assert (dg["p_in"] - dg["p_out"]) == pytest.approx(do["p_in"] - do["p_out"], rel=0.01)
+    assert compare(s16.fields(), of, ("T",))["T"] <= 1e-3
+
+
 # ------------------------------------------------------------------ full-size workloads
 # The benchmark workloads at their real sizes, in the configuration the
 # autotuner picks (as bench.py runs them); the oracle checks sampled cases

@@ -568,6 +568,22 @@ __device__ __forceinline__ void store9x2(const Ctx<R>& c, View dst, uint32_t o, 
         Vec<S>::st2e(dst.r, o * (4u * E), (uint32_t)(d * c.plane * 4 + K) * E, a[d], b[d], c.scale);
 }
 
+// FP16 storage: whole four-set records of node o, from f and g (compute
+// type) and the already packed (h, q) words.
+template <typename R>
+__device__ __forceinline__ void store9x4h(const Ctx<R>& c, View dst, uint32_t o, const R f[9], const R g[9],
+                                          const uint32_t hq[9])
+{
+    static_assert(SET_F == 0 && SET_G == 1 && SET_H == 2 && SET_Q == 3, "record order f, g, h, q");
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        decltype(__builtin_amdgcn_raw_buffer_load_b64(dst.r, 0, 0, 0)) w;
+        w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f[d] * c.scale, g[d] * c.scale));
+        w[1] = hq[d];
+        __builtin_amdgcn_raw_buffer_store_b64(w, dst.r, o * 8u, (uint32_t)(d * c.plane) * 8u, 0);
+    }
+}
+
 // Store the 9 post-collision populations of a set at node index o.
 template <int SET, typename S, typename R>
 __device__ __forceinline__ void store9(const Ctx<R>& c, View dst, uint32_t o, const R x[9])
@@ -1301,10 +1317,22 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             // collision) last, so that few values are live at once
             do_h(H);
             do_q(Q);
-            store9x2<SET_H, S>(c, dst, o, H, Q);
-            do_f(F);
-            do_g(g);
-            store9x2<SET_F, S>(c, dst, o, F, g);
+            if constexpr (sizeof(S) == 2) {
+                // FP16: (h, q) packed into one word per direction right away,
+                // then whole 8-byte records stored (full cache lines per wave)
+                uint32_t hq[9];
+#pragma unroll
+                for (int d = 0; d < 9; ++d)
+                    hq[d] = __builtin_bit_cast(uint32_t, __floats2half2_rn(H[d] * c.scale, Q[d] * c.scale));
+                do_f(F);
+                do_g(g);
+                store9x4h(c, dst, o, F, g, hq);
+            } else {
+                store9x2<SET_H, S>(c, dst, o, H, Q);
+                do_f(F);
+                do_g(g);
+                store9x2<SET_F, S>(c, dst, o, F, g);
+            }
         } else {
             // each set pulled right before its collision
             do_g(g);

@@ -93,6 +93,10 @@ typedef struct lbm_case {
     double xc, yc, R;        /* initial interface geometry */
     double psi_bulk, psi_band; /* initial psi = psi_bulk + psi_band * 4 phi0 (1 - phi0) */
     double phi_noise;        /* amplitude of uniform noise added to the initial phi */
+    double p_jump;           /* initial pressure p = p_jump (3 phi0^2 - 2 phi0^3), phi0 without noise:
+                                the pressure whose gradient carries the CSF force 1.5 W |grad phi|^2
+                                of a tanh interface (Sec. 3), so a bubble may start at its Laplace
+                                jump sigma/R; a density ratio of 1000 needs it (0 = uniform p = 0) */
     uint64_t seed;           /* noise: k-th splitmix64 output for node k = y*nx + x */
     int64_t max_steps;       /* step budget of this case within a batched run; <= 0 = unlimited */
 } lbm_case;
@@ -128,7 +132,7 @@ size_t lbm_workspace_bytes(const lbm_case* cases, int32_t ncases);
 
 /* Validate the cases, lay out the workspace, build the tile and strip tables
  * and set the initial state of every case (tanh interface plus noise, linear
- * T, psi band, p = 0, u = 0; populations at rest equilibrium).  `workspace`
+ * T, psi band, p from p_jump, u = 0; populations at rest equilibrium).  `workspace`
  * is device memory of at least lbm_workspace_bytes(), 256-byte aligned, owned
  * by the caller and used for everything the library keeps on the device (the
  * library allocates no device memory); `stream` is a hipStream_t (NULL =

@@ -297,13 +297,17 @@ static double phi_clean(const orc_case* c, int i, int j)
     return 0.5 + 0.5 * tanh(2.0 * d / c->W);
 }
 
-static void set_rest_equilibrium(orc_state* s, const double* phi, const double* T, const double* psi)
+/* Rest equilibrium (u = 0) of all four sets.  For g at u = 0 the central
+ * moment equilibria of Sec. 4.2 reduce to those of w_a p (zeroth p, second
+ * p c_s^2, fourth p c_s^4), so g_a = w_a p; p = NULL means p = 0. */
+static void set_rest_equilibrium(orc_state* s, const double* phi, const double* T, const double* psi,
+                                 const double* p)
 {
     const size_t n = s->n;
     for (int a = 0; a < 9; ++a) {
         for (size_t k = 0; k < n; ++k) {
             s->pop[(0 * 9 + a) * n + k] = WT[a] * phi[k];
-            s->pop[(1 * 9 + a) * n + k] = 0.0; /* p = 0, u = 0: g_eq = 0 */
+            s->pop[(1 * 9 + a) * n + k] = p ? WT[a] * p[k] : 0.0;
             s->pop[(2 * 9 + a) * n + k] = WT[a] * T[k];
             s->pop[(3 * 9 + a) * n + k] = WT[a] * psi[k];
         }
@@ -352,6 +356,7 @@ orc_state* orc_create(const orc_case* c)
     double* phi0 = alloc_d(s->n);
     double* T0 = alloc_d(s->n);
     double* psi0 = alloc_d(s->n);
+    double* p0 = alloc_d(s->n);
     for (int j = 0; j < s->ny; ++j)
         for (int i = 0; i < s->nx; ++i) {
             const size_t k = (size_t)j * s->nx + i;
@@ -359,8 +364,13 @@ orc_state* orc_create(const orc_case* c)
             phi0[k] = pc + c->phi_noise * noise_unit(c->seed, k);
             T0[k] = wall_T(c, (double)i);
             psi0[k] = c->psi_bulk + c->psi_band * 4.0 * pc * (1.0 - pc);
+            /* integral of the CSF weight 1.5 W |grad phi|^2 (Sec. 3) across the
+             * tanh profile, |grad phi| = 4 phi (1 - phi) / W: d p / d phi =
+             * p_jump 6 phi (1 - phi) */
+            p0[k] = c->p_jump * pc * pc * (3.0 - 2.0 * pc);
         }
-    set_rest_equilibrium(s, phi0, T0, psi0);
+    set_rest_equilibrium(s, phi0, T0, psi0, p0);
+    free(p0);
     free(phi0);
     free(T0);
     free(psi0);
@@ -380,7 +390,7 @@ void orc_free(orc_state* s)
 
 void orc_load_fields(orc_state* s, const double* phi, const double* T, const double* psi)
 {
-    set_rest_equilibrium(s, phi, T, psi);
+    set_rest_equilibrium(s, phi, T, psi, NULL);
 }
 
 int64_t orc_steps_done(const orc_state* s) { return s->step; }

@@ -37,6 +37,7 @@ typedef struct orc_case {
     double  s_lam, w_lam;  /* s/lambda and w/lambda of the surfactant chemical potential */
     double  Fext_x, Fext_y, gravity;
     double  xc, yc, R, psi_bulk, psi_band, phi_noise;
+    double  p_jump;      /* initial pressure p = p_jump (3 phi^2 - 2 phi^3) of the clean phi (0: p = 0) */
     uint64_t seed;
 } orc_case;
 

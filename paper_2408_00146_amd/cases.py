@@ -43,7 +43,7 @@ def base(**kw) -> dict:
         rho_A=1.0, rho_B=0.1, nu_A=0.1, nu_B=0.1, alpha_A=0.05, alpha_B=0.05,
         D_psi=0.01, M_phi=0.1, W=W, s_lam=s_lam, w_lam=w_lam,
         Fext_x=0.0, Fext_y=0.0, gravity=0.0,
-        xc=40.0, yc=32.0, R=10.0, psi_bulk=0.0, psi_band=0.1, phi_noise=1e-6, seed=0,
+        xc=40.0, yc=32.0, R=10.0, psi_bulk=0.0, psi_band=0.1, phi_noise=1e-6, p_jump=0.0, seed=0,
         max_steps=0,
     )
     c.update(kw)
@@ -146,6 +146,16 @@ def static_bubble(n: int = 64, R: float = 12.0, sigma: float = 1e-3, rho_ratio: 
     return base(nx=n, ny=n, precision=precision, wall=[0, 0, 0, 0], t_bc=[0, 0, 0, 0],
                 sigma0=sigma, sigma_T=0.0, sigma_TT=0.0, beta_s=0.0, rho_A=1.0, rho_B=1.0 / rho_ratio,
                 W=W, xc=n / 2.0, yc=n / 2.0, R=R, gradT=0.0, psi_band=0.0, phi_noise=0.0)
+
+
+def laplace_hdr(n: int = 200, R: float = 25.0, sigma: float = 1e-3, precision: int = FP64) -> dict:
+    """Static bubble at density ratio 1000 and viscosity ratio 100 in a
+    periodic box (the Laplace test of Sec. 5.1), started at its Laplace
+    pressure (from p = 0, or from a pressure step p_jump * phi0, a bubble of
+    radius 20 at sigma = 4e-3 diverges within 50 steps)."""
+    p = static_bubble(n=n, R=R, sigma=sigma, rho_ratio=1000.0, W=5.0, precision=precision)
+    p.update(nu_A=0.1, nu_B=1.0, p_jump=sigma / R)
+    return p
 
 
 def poiseuille(ny: int = 32, nx: int = 4, F: float = 1e-6, nu: float = 0.5) -> dict:

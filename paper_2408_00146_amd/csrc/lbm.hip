@@ -241,14 +241,28 @@ __device__ __forceinline__ double noise_unit(uint64_t seed, uint64_t k)
 
 struct InitDev {
     int32_t kind, pad;
-    double xc, yc, R, W, psi_bulk, psi_band, phi_noise;
+    double xc, yc, R, W, psi_bulk, psi_band, phi_noise, p_jump;
     uint64_t seed;
 };
+
+// Clean initial phase profile: the tanh equilibrium of the conservative
+// Allen-Cahn equation (Sec. 3) across the circle or band of radius R.
+__device__ double init_phi(const InitDev& in, int x, int y)
+{
+    if (in.kind == 2) return 0.0;
+    double d;
+    if (in.kind == 1) d = in.R - fabs((double)y - in.yc);
+    else d = in.R - sqrt(((double)x - in.xc) * ((double)x - in.xc) + ((double)y - in.yc) * ((double)y - in.yc));
+    return 0.5 + 0.5 * tanh(2.0 * d / in.W);
+}
 
 // Where the post-streaming state of a case comes from: FP64 population
 // planes [4][9][ny][nx], or FP64 fields phi/T/psi (rest equilibrium,
 // g = 0 for p = 0, u = 0), or the built-in initial condition (tanh
-// interface of Sec. 3 plus noise, linear wall law for T, psi band).
+// interface of Sec. 3 plus noise, linear wall law for T, psi band,
+// p = p_jump (3 phi^2 - 2 phi^3) of the clean phi, the integral of the CSF
+// weight 1.5 W |grad phi|^2 across a tanh interface; the rest equilibrium
+// of g at u = 0 is w_a p).
 struct StateSrc {
     const double* pops;
     const double *phi, *T, *psi;
@@ -259,22 +273,17 @@ __device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, 
 {
     const int64_t n = (int64_t)cd.nx * cd.ny, k = (int64_t)y * cd.nx + x;
     if (s.pops) return s.pops[(int64_t)(set * 9 + a) * n + k];
-    if (set == SET_G) return 0.0;
+    if (set == SET_G && (s.phi || s.in.p_jump == 0.0)) return 0.0;
     double X;
     if (s.phi) {
         X = set == SET_F ? s.phi[k] : (set == SET_H ? s.T[k] : s.psi[k]);
     } else if (set == SET_H) {
         X = cd.T0 + cd.gradT * ((double)x - cd.xT0);
     } else {
-        double pc = 0.0;
-        if (s.in.kind != 2) {
-            double d;
-            if (s.in.kind == 1) d = s.in.R - fabs((double)y - s.in.yc);
-            else d = s.in.R - sqrt(((double)x - s.in.xc) * ((double)x - s.in.xc) + ((double)y - s.in.yc) * ((double)y - s.in.yc));
-            pc = 0.5 + 0.5 * tanh(2.0 * d / s.in.W);
-        }
-        X = set == SET_F ? pc + s.in.phi_noise * noise_unit(s.in.seed, (uint64_t)k)
-                         : s.in.psi_bulk + s.in.psi_band * 4.0 * pc * (1.0 - pc);
+        const double pc = init_phi(s.in, x, y);
+        if (set == SET_F) X = pc + s.in.phi_noise * noise_unit(s.in.seed, (uint64_t)k);
+        else if (set == SET_G) X = s.in.p_jump * pc * pc * (3.0 - 2.0 * pc);
+        else X = s.in.psi_bulk + s.in.psi_band * 4.0 * pc * (1.0 - pc);
     }
     return wt(a) * X;
 }
@@ -531,6 +540,7 @@ int validate(const lbm_case& c, int i)
     for (auto& p : pos)
         if (!(p.v > 0) || !std::isfinite(p.v)) return fail(LBM_E_INVAL, "case %d: %s must be finite and > 0", i, p.name);
     if (c.sigma_law == LBM_SIGMA_PAPER && !(c.T_ref != 0)) return fail(LBM_E_INVAL, "case %d: T_ref must be nonzero", i);
+    if (!std::isfinite(c.p_jump)) return fail(LBM_E_INVAL, "case %d: p_jump must be finite", i);
     return LBM_OK;
 }
 
@@ -599,6 +609,7 @@ InitDev make_init(const lbm_case& c)
     in.psi_bulk = c.psi_bulk;
     in.psi_band = c.psi_band;
     in.phi_noise = c.phi_noise;
+    in.p_jump = c.p_jump;
     in.seed = c.seed;
     return in;
 }

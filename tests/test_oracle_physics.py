@@ -119,6 +119,59 @@ def test_laplace_law(O):
     assert dps[1] / dps[0] == pytest.approx(2.0, rel=0.01)
 
 
+def test_laplace_law_density_ratio_1000(O):
+    """Static bubble at density ratio 1000 and viscosity ratio 100 (the
+    Laplace test of Sec. 5.1), started at its Laplace pressure: the pressure
+    jump, averaged over the acoustic oscillation of the box, is sigma / R
+    within 5 % and linear in sigma to 1 % (R = 20, W = 5, 80x80 periodic)."""
+    R = 20.0
+    dps = []
+    for sigma in (1e-3, 4e-3):
+        o = O.Oracle(cases.laplace_hdr(n=80, R=R, sigma=sigma))
+        o.step(1000)
+        samples = []
+        for _ in range(25):
+            o.step(20)
+            d = o.diag()
+            samples.append(d["p_in"] - d["p_out"])
+        assert d["nonfinite"] == 0 and d["phi_max"] < 1.001
+        dps.append(float(np.mean(samples)))
+        assert dps[-1] == pytest.approx(sigma / R, rel=0.05)
+    assert dps[1] / dps[0] == pytest.approx(4.0, rel=0.01)
+
+
+def test_initial_pressure_is_rest_equilibrium(O):
+    """With p_jump set, the initial g is the rest equilibrium (u = 0) of a
+    pressure that rises across the tanh interface by the CSF weight
+    1.5 W |grad phi|^2 (Sec. 3): p(r) = p_jump * integral from r to infinity of
+    1.5 W (d phi0 / ds)^2 ds, checked here by quadrature.  g is w_a p in
+    every direction (so its first moments vanish), and its raw moments are
+    the equilibrium of Sec. 4.2 at that p and u = 0."""
+    from scipy.integrate import quad
+
+    c = cases.laplace_hdr(n=32, R=8.0, sigma=2e-3)
+    o = O.Oracle(c)
+    g = o.populations()[1]
+    W, R = c["W"], c["R"]
+    dist = np.hypot(np.arange(32)[None, :] - 16.0, np.arange(32)[:, None] - 16.0)
+    phi0 = 0.5 + 0.5 * np.tanh(2.0 * (R - dist) / W)
+
+    def csf_integral(r):
+        dphi = lambda s_: -1.0 / (W * np.cosh(2.0 * (R - s_) / W) ** 2)
+        return quad(lambda s_: 1.5 * W * dphi(s_) ** 2, r, R + 20 * W, epsabs=1e-15, epsrel=1e-12)[0]
+
+    psum = g.sum(axis=0)
+    for k in ((16, 16), (16, 20), (16, 23), (16, 25), (13, 22), (3, 3)):
+        assert psum[k] == pytest.approx(c["p_jump"] * csf_integral(dist[k]), rel=1e-9, abs=1e-15 * c["p_jump"])
+    # g_a = w_a p: the same p in every direction, so the first moments vanish
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    assert np.abs(g / w[:, None, None] - psum[None]).max() <= 1e-14 * c["p_jump"]
+    for k in ((16, 16), (16, 23), (3, 3)):
+        rho = c["rho_A"] + phi0[k] * (c["rho_B"] - c["rho_A"])
+        # at u = 0 central and raw moments coincide: P g against the equilibria
+        assert np.abs(O.matrix_P() @ g[:, k[0], k[1]] - O.eq_g(psum[k], rho, 0.0, 0.0)).max() <= 1e-14 * c["p_jump"]
+
+
 def test_marangoni_flat_interface(O):
     """A flat interface under T = T0 + A cos(kx) with linear sigma(T) feels
     the tangential stress d sigma/dx; the steady Stokes response to that

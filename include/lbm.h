@@ -91,7 +91,8 @@ typedef struct lbm_case {
     double Fext_x, Fext_y;   /* constant body force */
     double gravity;          /* buoyancy F_y -= (rho - rho_A) * gravity */
     double xc, yc, R;        /* initial interface geometry */
-    double psi_bulk, psi_band; /* initial psi = psi_bulk + psi_band * 4 phi0 (1 - phi0) */
+    double psi_bulk, psi_band; /* initial psi = psi_bulk + psi_gradx (x - xT0) + psi_band * 4 phi0 (1 - phi0) */
+    double psi_gradx;        /* linear initial background of psi along x (between Dirichlet psi walls) */
     double phi_noise;        /* amplitude of uniform noise added to the initial phi */
     double p_jump;           /* initial pressure p = p_jump (3 phi0^2 - 2 phi0^3), phi0 without noise:
                                 the pressure whose gradient carries the CSF force 1.5 W |grad phi|^2

@@ -363,7 +363,7 @@ orc_state* orc_create(const orc_case* c)
             const double pc = phi_clean(c, i, j);
             phi0[k] = pc + c->phi_noise * noise_unit(c->seed, k);
             T0[k] = wall_T(c, (double)i);
-            psi0[k] = c->psi_bulk + c->psi_band * 4.0 * pc * (1.0 - pc);
+            psi0[k] = c->psi_bulk + c->psi_gradx * ((double)i - c->xT0) + c->psi_band * 4.0 * pc * (1.0 - pc);
             /* integral of the CSF weight 1.5 W |grad phi|^2 (Sec. 3) across the
              * tanh profile, |grad phi| = 4 phi (1 - phi) / W: d p / d phi =
              * p_jump 6 phi (1 - phi) */

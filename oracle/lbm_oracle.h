@@ -36,7 +36,9 @@ typedef struct orc_case {
     double  rho_A, rho_B, nu_A, nu_B, alpha_A, alpha_B, D_psi, M_phi, W;
     double  s_lam, w_lam;  /* s/lambda and w/lambda of the surfactant chemical potential */
     double  Fext_x, Fext_y, gravity;
-    double  xc, yc, R, psi_bulk, psi_band, phi_noise;
+    double  xc, yc, R, psi_bulk, psi_band;
+    double  psi_gradx;   /* initial psi adds psi_gradx (x - xT0): linear background along x */
+    double  phi_noise;
     double  p_jump;      /* initial pressure p = p_jump (3 phi^2 - 2 phi^3) of the clean phi (0: p = 0) */
     uint64_t seed;
 } orc_case;

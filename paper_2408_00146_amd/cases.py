@@ -43,7 +43,7 @@ def base(**kw) -> dict:
         rho_A=1.0, rho_B=0.1, nu_A=0.1, nu_B=0.1, alpha_A=0.05, alpha_B=0.05,
         D_psi=0.01, M_phi=0.1, W=W, s_lam=s_lam, w_lam=w_lam,
         Fext_x=0.0, Fext_y=0.0, gravity=0.0,
-        xc=40.0, yc=32.0, R=10.0, psi_bulk=0.0, psi_band=0.1, phi_noise=1e-6, p_jump=0.0, seed=0,
+        xc=40.0, yc=32.0, R=10.0, psi_bulk=0.0, psi_band=0.1, phi_noise=1e-6, p_jump=0.0, psi_gradx=0.0, seed=0,
         max_steps=0,
     )
     c.update(kw)
@@ -198,3 +198,56 @@ def thermocapillary_nf(nx: int = 192, ny: int = 96, R: float = 12.0, G: float = 
     return base(nx=nx, ny=ny, R=R, W=4.0, xc=nx / 2.0, yc=ny / 2.0, gradT=G, xT0=nx / 2.0,
                 sigma0=1e-3, sigma_T=sigma_T, sigma_TT=0.0, beta_s=0.0, nu_A=nu, nu_B=nu,
                 alpha_A=alpha, alpha_B=alpha, psi_band=0.0, phi_noise=0.0)
+
+
+# ------------------------------------------------- the paper's migration problem
+
+def srf_channel(M1: float = 0.0, M2: float = 5.0, beta: float = 0.0, psi_L: float = 0.4, psi_R: float = 0.1,
+                L: int = 600, D_over_H: float = 0.1, x0_over_L: float = 0.25, Re: float = 5.0, Ma: float = 0.25,
+                rho_ratio: float = 1000.0, mu_ratio: float = 100.0, sigma0: float = 5e-3, W: float = 5.0,
+                M_phi: float = 0.1, M_psi: float = 0.01, Pi: float = 8.33, Ex: float = 0.16,
+                precision: int = FP32) -> dict:
+    """The surfactant-laden bubble migration problem of Sec. 2 and Sec. 6 from
+    its dimensionless groups, in lattice units.
+
+    Domain L x H with H = L/2; no-slip walls at x = -1/2 (hot, T_H = 1, psi_L)
+    and x = L - 1/2 (cold, T_C = 0, psi_R), periodic in y; T and psi start
+    linear between the walls, T_ref = 0.5 at mid-channel.  Bubble of diameter
+    D = D_over_H H at (x0_over_L L, H/2), started at the Laplace pressure of
+    its surface tension there.  Printed (additive) sigma law with
+    sigma_T = M1 sigma0 / dT and sigma_TT = M2 sigma0 / dT^2 (dT = 1).
+    Velocity scale U_o = (sigma0/mu_A)(R/L)|M1 + M2| (Sec. 6); Re = U_o R/nu_A
+    and Ma = U_o R/alpha_A (Sec. 2.1) fix nu_A and alpha_A (rho_A = 1);
+    rho_B = rho_A/rho_ratio, mu_B = mu_A/mu_ratio, alpha_B = alpha_A.
+    Surfactant chemical potential from Pi and Ex; D_psi = M_psi."""
+    H = L // 2
+    R = 0.5 * D_over_H * H
+    dT = 1.0
+    sT, sTT = M1 * sigma0 / dT, M2 * sigma0 / dT ** 2
+    # U_o mu_A is fixed by sigma0, R/L, M1 + M2; Re then fixes mu_A = nu_A (rho_A = 1)
+    Uo_muA = sigma0 * (R / L) * abs(M1 + M2)
+    nu_A = (Uo_muA * R / Re) ** 0.5
+    Uo = Uo_muA / nu_A
+    alpha = Uo * R / Ma
+    rho_B = 1.0 / rho_ratio
+    nu_B = nu_A / mu_ratio / rho_B
+    T_of = lambda x: 1.0 - (x + 0.5) / L
+    xb, yb = x0_over_L * L - 0.5, 0.5 * H - 0.5
+    psi_b = psi_L + (psi_R - psi_L) * (xb + 0.5) / L
+    sig_b = sigma0 + sigma0 * beta * (T_of(xb) / 0.5) * np.log(1.0 - psi_b) + sT * (T_of(xb) - 0.5) \
+        + sTT * (T_of(xb) - 0.5) ** 2
+    s_lam, w_lam = surfactant_ratios(W, Pi, Ex)
+    return base(nx=L, ny=H, precision=precision, wall=[1, 1, 0, 0], t_bc=[1, 1, 0, 0], psi_bc=[1, 1, 0, 0],
+                psi_w=[psi_L, psi_R, 0.0, 0.0], T0=T_of(0.0), gradT=-dT / L, xT0=0.0,
+                sigma_law=SIGMA_PAPER, sigma0=sigma0, sigma_T=sT, sigma_TT=sTT, T_ref=0.5, beta_s=beta,
+                psi_inf=1.0, rho_A=1.0, rho_B=rho_B, nu_A=nu_A, nu_B=nu_B, alpha_A=alpha, alpha_B=alpha,
+                D_psi=M_psi, M_phi=M_phi, W=W, s_lam=s_lam, w_lam=w_lam, xc=xb, yc=yb, R=R,
+                psi_bulk=psi_L + (psi_R - psi_L) * 0.5 / L, psi_gradx=(psi_R - psi_L) / L, psi_band=0.0,
+                phi_noise=0.0, p_jump=sig_b / R)
+
+
+def srf_scales(p: dict) -> dict:
+    """Velocity and time scales of an srf_channel case: U_o and T_o = R/U_o."""
+    M12 = abs(p["sigma_T"] + p["sigma_TT"]) / p["sigma0"]
+    Uo = p["sigma0"] / (p["rho_A"] * p["nu_A"]) * (p["R"] / p["nx"]) * M12
+    return {"Uo": Uo, "To": p["R"] / Uo}

@@ -241,7 +241,7 @@ __device__ __forceinline__ double noise_unit(uint64_t seed, uint64_t k)
 
 struct InitDev {
     int32_t kind, pad;
-    double xc, yc, R, W, psi_bulk, psi_band, phi_noise, p_jump;
+    double xc, yc, R, W, psi_bulk, psi_band, psi_gradx, xT0, phi_noise, p_jump;
     uint64_t seed;
 };
 
@@ -259,7 +259,7 @@ __device__ double init_phi(const InitDev& in, int x, int y)
 // Where the post-streaming state of a case comes from: FP64 population
 // planes [4][9][ny][nx], or FP64 fields phi/T/psi (rest equilibrium,
 // g = 0 for p = 0, u = 0), or the built-in initial condition (tanh
-// interface of Sec. 3 plus noise, linear wall law for T, psi band,
+// interface of Sec. 3 plus noise, linear wall law for T, psi background and band,
 // p = p_jump (3 phi^2 - 2 phi^3) of the clean phi, the integral of the CSF
 // weight 1.5 W |grad phi|^2 across a tanh interface; the rest equilibrium
 // of g at u = 0 is w_a p).
@@ -283,7 +283,7 @@ __device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, 
         const double pc = init_phi(s.in, x, y);
         if (set == SET_F) X = pc + s.in.phi_noise * noise_unit(s.in.seed, (uint64_t)k);
         else if (set == SET_G) X = s.in.p_jump * pc * pc * (3.0 - 2.0 * pc);
-        else X = s.in.psi_bulk + s.in.psi_band * 4.0 * pc * (1.0 - pc);
+        else X = s.in.psi_bulk + s.in.psi_gradx * ((double)x - s.in.xT0) + s.in.psi_band * 4.0 * pc * (1.0 - pc);
     }
     return wt(a) * X;
 }
@@ -541,6 +541,7 @@ int validate(const lbm_case& c, int i)
         if (!(p.v > 0) || !std::isfinite(p.v)) return fail(LBM_E_INVAL, "case %d: %s must be finite and > 0", i, p.name);
     if (c.sigma_law == LBM_SIGMA_PAPER && !(c.T_ref != 0)) return fail(LBM_E_INVAL, "case %d: T_ref must be nonzero", i);
     if (!std::isfinite(c.p_jump)) return fail(LBM_E_INVAL, "case %d: p_jump must be finite", i);
+    if (!std::isfinite(c.psi_gradx)) return fail(LBM_E_INVAL, "case %d: psi_gradx must be finite", i);
     return LBM_OK;
 }
 
@@ -608,6 +609,8 @@ InitDev make_init(const lbm_case& c)
     in.W = c.W;
     in.psi_bulk = c.psi_bulk;
     in.psi_band = c.psi_band;
+    in.psi_gradx = c.psi_gradx;
+    in.xT0 = c.xT0;
     in.phi_noise = c.phi_noise;
     in.p_jump = c.p_jump;
     in.seed = c.seed;

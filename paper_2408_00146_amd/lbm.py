@@ -45,7 +45,7 @@ class LbmCase(C.Structure):
         ("W", C.c_double), ("s_lam", C.c_double), ("w_lam", C.c_double),
         ("Fext_x", C.c_double), ("Fext_y", C.c_double), ("gravity", C.c_double),
         ("xc", C.c_double), ("yc", C.c_double), ("R", C.c_double),
-        ("psi_bulk", C.c_double), ("psi_band", C.c_double), ("phi_noise", C.c_double),
+        ("psi_bulk", C.c_double), ("psi_band", C.c_double), ("psi_gradx", C.c_double), ("phi_noise", C.c_double),
         ("p_jump", C.c_double), ("seed", C.c_uint64), ("max_steps", C.c_int64),
     ]
 

@@ -1,0 +1,53 @@
+"""Host-side checks of the case constructors: the dimensionless groups of
+the paper's migration problem (Sec. 2.1, Sec. 6) survive the conversion to
+lattice units, and the oracle's initial state honours the walls' values."""
+import numpy as np
+import pytest
+
+from paper_2408_00146_amd import cases
+
+
+@pytest.mark.parametrize("M1,M2,beta,rho_ratio", [(0.0, 5.0, 0.4, 1000.0), (0.0, 1.25, 0.0, 100.0),
+                                                  (-2.5, 0.0, 0.2, 1000.0)])
+def test_srf_channel_groups(M1, M2, beta, rho_ratio):
+    p = cases.srf_channel(M1=M1, M2=M2, beta=beta, rho_ratio=rho_ratio)
+    L, H, R = p["nx"], p["ny"], p["R"]
+    assert (L, H) == (600, 300) and 2 * R == pytest.approx(0.1 * H)
+    sc = cases.srf_scales(p)
+    Uo = sc["Uo"]
+    muA, muB = p["rho_A"] * p["nu_A"], p["rho_B"] * p["nu_B"]
+    # U_o balances the viscous stress mu_A U/R with the thermal Marangoni stress (Sec. 6)
+    assert Uo == pytest.approx(p["sigma0"] / muA * (R / L) * abs(M1 + M2), rel=1e-12)
+    assert Uo * R / p["nu_A"] == pytest.approx(5.0, rel=1e-12)          # Re
+    assert Uo * R / p["alpha_A"] == pytest.approx(0.25, rel=1e-12)      # Ma
+    assert p["rho_A"] / p["rho_B"] == pytest.approx(rho_ratio, rel=1e-12)
+    assert muA / muB == pytest.approx(100.0, rel=1e-12)
+    assert p["alpha_A"] == p["alpha_B"]
+    dT = 1.0
+    assert p["sigma_T"] * dT / p["sigma0"] == pytest.approx(M1, abs=1e-12)
+    assert p["sigma_TT"] * dT ** 2 / p["sigma0"] == pytest.approx(M2, abs=1e-12)
+    # Pi = lambda W^2 / (8 sigma0) and Ex = 4 s / (w W^2) with s = 8 sigma0
+    W = p["W"]
+    s_over_lambda, w_over_lambda = p["s_lam"], p["w_lam"]
+    assert W ** 2 / s_over_lambda == pytest.approx(8.33, rel=1e-12)
+    assert 4 * s_over_lambda / (w_over_lambda * W ** 2) == pytest.approx(0.16, rel=1e-12)
+    # wall temperature: T_H = 1 at x = -1/2, T_C = 0 at x = L - 1/2, T_ref = 0.5 mid-channel
+    T = lambda x: p["T0"] + p["gradT"] * (x - p["xT0"])
+    assert T(-0.5) == pytest.approx(1.0) and T(L - 0.5) == pytest.approx(0.0, abs=1e-12)
+    assert T(L / 2 - 0.5) == pytest.approx(p["T_ref"])
+    # initial psi background meets the Dirichlet values at the walls
+    psi = lambda x: p["psi_bulk"] + p["psi_gradx"] * (x - p["xT0"])
+    assert psi(-0.5) == pytest.approx(p["psi_w"][0]) and psi(L - 0.5) == pytest.approx(p["psi_w"][1])
+    assert p["wall"] == [1, 1, 0, 0] and p["t_bc"] == [1, 1, 0, 0] and p["psi_bc"] == [1, 1, 0, 0]
+
+
+def test_oracle_initial_psi_background(oracle_mod):
+    """psi_gradx: the oracle's initial psi is the linear background (plus the
+    interface band) at every node."""
+    p = cases.srf_channel(L=120)
+    o = oracle_mod.Oracle(p)
+    f = o.fields()
+    x = np.arange(p["nx"], dtype=float)
+    expect = p["psi_bulk"] + p["psi_gradx"] * (x - p["xT0"])
+    assert np.abs(f["psi"] - expect[None, :]).max() <= 1e-15
+    assert f["psi"][0, 0] > f["psi"][0, -1]

@@ -235,8 +235,8 @@ class Solver:
         torch = self._torch
         nx, ny = self.cases[case]["nx"], self.cases[case]["ny"]
         with self._on_stream():
-            ts = [torch.as_tensor(np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (ny, nx))))
-                  .to(self.device) for v in (phi, T, psi)]
+            ts = [torch.from_numpy(np.broadcast_to(np.asarray(v, dtype=np.float64), (ny, nx)).copy()).to(self.device)
+                  for v in (phi, T, psi)]
             _check(lib().lbm_load_fields(self._h, case, *[C.c_void_p(t.data_ptr()) for t in ts], 1))
         self.synchronize()
 

@@ -48,6 +48,10 @@ def workload(name: str):
         return cases.config_batched()
     if name == "large_plus_small":
         return cases.config_large_plus_small()
+    if name == "srf_600x300x4":
+        # the paper's migration problem (Sec. 6): four 600x300 channels, M2 5 / 1.25, beta 0 / 0.4
+        return [cases.srf_channel(M2=m2, beta=b, psi_L=pl, rho_ratio=10.0)
+                for m2, b, pl in ((5.0, 0.0, 0.4), (5.0, 0.4, 0.4), (5.0, 0.4, 0.6), (1.25, 0.4, 0.4))]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -109,7 +113,7 @@ def cpu_baseline(params: dict, budget_s: float = 15.0) -> dict:
 
 
 COMPARE = ("fp32_1024x512", "fp16s_2048x1024", "fp32_2048x1024", "fp64_2048x1024", "batched64",
-           "large_plus_small")
+           "large_plus_small", "srf_600x300x4")
 
 
 def measure(name: str, steps: int, warmup: int) -> dict:

@@ -605,3 +605,26 @@ def test_srf_equilibrium_positions(env):
         assert abs(x - x_eq) <= 0.015, (b, pl, x)
         assert abs(U) < 2e-3, (b, pl, U)
     assert abs((s.reduce(0)["xc"] + 0.5) / ps[0]["nx"] - 0.5) < 0.002
+
+
+def test_nf_migration_slowed_by_surfactant(env):
+    """The paper's normal-fluid runs (Sec. 6: M1 = -2.5, M2 = 0, psi from 0.1
+    at the hot wall to 0.4 at the cold one, bubble launched at x/L = 0.75),
+    beta in {0, 0.2, 0.3, 0.4} in one FP32 handle at density ratio 10: every
+    bubble migrates towards the hot wall at a steady speed, and the speed
+    falls as beta rises (measured after 150000 steps, t* = 100: U/U_o =
+    -0.18, -0.15, -0.13, -0.12)."""
+    lbm, _ = env
+    betas = (0.0, 0.2, 0.3, 0.4)
+    ps = [cases.srf_channel(M1=-2.5, M2=0.0, beta=b, psi_L=0.1, psi_R=0.4, x0_over_L=0.75, rho_ratio=10.0)
+          for b in betas]
+    s = lbm.Solver(ps)
+    s.step(100_000)
+    x1 = [s.reduce(i)["xc"] for i in range(len(ps))]
+    s.step(50_000)
+    Uo = cases.srf_scales(ps[0])["Uo"]
+    d = [s.reduce(i) for i in range(len(ps))]
+    U = [di["ux"] / Uo for di in d]
+    assert all(di["xc"] < xa for di, xa in zip(d, x1)), (x1, [di["xc"] for di in d])
+    assert all(u < -0.05 for u in U), U
+    assert all(abs(a) > abs(b) for a, b in zip(U, U[1:])), U

@@ -136,7 +136,9 @@ size_t lbm_workspace_bytes(const lbm_case* cases, int32_t ncases);
  * T, psi band, p from p_jump, u = 0; populations at rest equilibrium).  `workspace`
  * is device memory of at least lbm_workspace_bytes(), 256-byte aligned, owned
  * by the caller and used for everything the library keeps on the device (the
- * library allocates no device memory); `stream` is a hipStream_t (NULL =
+ * library allocates no device memory of its own; only the host-memory variants
+ * of the field and population transfers below stage through a temporary
+ * device buffer); `stream` is a hipStream_t (NULL =
  * default stream).  LBM_E_INVAL for: FP64 cases mixed with FP32/FP16S cases
  * in one handle; a case whose population buffer (36 values per node in its
  * storage type, pitch nx rounded up to 64) exceeds 4 GiB, the reach of the

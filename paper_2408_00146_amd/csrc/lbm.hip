@@ -438,6 +438,9 @@ size_t elem_bytes(int prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
+// MI355X last-level (Infinity) cache shared by the XCDs.
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
+
 // Nodes per population / reference plane: ny rows of the pitch plus kPlanePad
 // nodes, so that the 36 planes of a buffer do not start at one power-of-two
 // stride.
@@ -865,6 +868,12 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         h->dev.push_back(make_dev(cases[i], base, base + b, r ? base + 2 * b : nullptr, r ? base + 2 * b + r : nullptr));
         o += 2 * (b + r);
     }
+    // A step reads one buffer of every case and writes the other: when the
+    // populations of the handle exceed the last-level cache, whole-record
+    // FP16 stores are non-temporal (a step's output is read back from HBM
+    // anyway); when they fit, the next step finds them in that cache.
+    const bool nt = o - L.off_pops > kLastLevelCacheBytes;
+    for (auto& d : h->dev) d.nt_store = nt ? 1 : 0;
     std::vector<TileRec> tiles;
     auto upload = [&](TileRec* dst) -> int {
         if (tiles.empty()) return LBM_OK;

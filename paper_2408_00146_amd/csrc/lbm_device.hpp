@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // ------------------------------------------------------------- lattice
@@ -60,6 +62,8 @@ struct CaseDev {
     int64_t max_steps;  // <= 0: unlimited
     uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
     uint32_t ref_bytes; // bytes of one reference buffer (4 FP16 values per node)
+    int32_t nt_store;   // whole-record FP16 stores non-temporal (the handle's buffers exceed the last-level cache)
+    int32_t pad0;
     void* buf[2];       // ping-pong population buffers
     __half* rbuf[2];    // per-node references [plane][4 = phi, psi, p*, T] of each buffer (refs only)
 };
@@ -74,6 +78,7 @@ struct Ctx {
     int nx, ny, pitch, wallx, wally, law;
     int tbc, pbc;  // bit s set: Dirichlet T / psi on side s (no dynamic array indexing: keeps Ctx in registers)
     int plane;     // elements per plane; 36 planes fit a 4 GiB buffer resource
+    int nt;        // whole-record FP16 stores non-temporal
     const double* psi_w;  // wall values read from global memory (a select over struct fields would defeat SROA)
     R T0, gradT, xT0;
     R s0, sT, sTT, Tref, beta, inv_psi_inf;
@@ -89,6 +94,7 @@ struct Ctx {
     {
         nx = c.nx; ny = c.ny; pitch = c.pitch; wallx = c.wallx; wally = c.wally; law = c.law;
         plane = (int)c.plane;
+        nt = c.nt_store;
         tbc = (c.tbc[0] ? 1 : 0) | (c.tbc[1] ? 2 : 0) | (c.tbc[2] ? 4 : 0) | (c.tbc[3] ? 8 : 0);
         pbc = (c.pbc[0] ? 1 : 0) | (c.pbc[1] ? 2 : 0) | (c.pbc[2] ? 4 : 0) | (c.pbc[3] ? 8 : 0);
         psi_w = c.psi_w;
@@ -148,6 +154,16 @@ __device__ __forceinline__ __half enc<__half, float>(float v, float scale) { ret
 // scalar (SGPR) byte offset per (set, direction) -- no per-access 64-bit
 // address arithmetic.  Accesses outside the resource return 0 / are dropped.
 constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+// Cache policy of stores whose wave writes whole 64-byte lines (FP16 storage:
+// 8-byte records of 64 consecutive nodes), used when the handle's buffers
+// exceed the last-level cache: non-temporal, the lines go to HBM without
+// taking cache space from the halo rows other workgroups still read.  When
+// the buffers fit in the last-level cache the next step reads them back
+// from there, and the default policy is faster.  Stores that write part of
+// each record (set pairs of FP32 / FP64 records) always keep the default
+// policy: the cache merges the halves of a line, and bypassing it doubles
+// the write traffic.
+constexpr int kStoreNT = 2;
 using Rsrc = __amdgpu_buffer_rsrc_t;
 
 __device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes)
@@ -321,12 +337,13 @@ __device__ __forceinline__ float ref_get(uint32_t lo, uint32_t hi)
     return __half2float(__ushort_as_half((unsigned short)((K & 1) ? (w >> 16) : (w & 0xffffu))));
 }
 // values already FP16-exact (the rounded moments), so the conversion is exact
-__device__ __forceinline__ void ref_st(Rsrc r, uint32_t node, float f, float q, float p, float t)
+__device__ __forceinline__ void ref_st(Rsrc r, uint32_t node, float f, float q, float p, float t, bool nt = false)
 {
     decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) w;
     w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f, q));
     w[1] = __builtin_bit_cast(uint32_t, __floats2half2_rn(p, t));
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, node * 8u, 0, 0);
+    if (nt) __builtin_amdgcn_raw_buffer_store_b64(w, r, node * 8u, 0, kStoreNT);
+    else __builtin_amdgcn_raw_buffer_store_b64(w, r, node * 8u, 0, 0);
 }
 
 // A population buffer as seen by one tile.
@@ -575,13 +592,18 @@ __device__ __forceinline__ void store9x4h(const Ctx<R>& c, View dst, uint32_t o,
                                           const uint32_t hq[9])
 {
     static_assert(SET_F == 0 && SET_G == 1 && SET_H == 2 && SET_Q == 3, "record order f, g, h, q");
+    auto put = [&](auto pol) {
 #pragma unroll
-    for (int d = 0; d < 9; ++d) {
-        decltype(__builtin_amdgcn_raw_buffer_load_b64(dst.r, 0, 0, 0)) w;
-        w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f[d] * c.scale, g[d] * c.scale));
-        w[1] = hq[d];
-        __builtin_amdgcn_raw_buffer_store_b64(w, dst.r, o * 8u, (uint32_t)(d * c.plane) * 8u, 0);
-    }
+        for (int d = 0; d < 9; ++d) {
+            decltype(__builtin_amdgcn_raw_buffer_load_b64(dst.r, 0, 0, 0)) w;
+            w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f[d] * c.scale, g[d] * c.scale));
+            w[1] = hq[d];
+            __builtin_amdgcn_raw_buffer_store_b64(w, dst.r, o * 8u, (uint32_t)(d * c.plane) * 8u, decltype(pol)::value);
+        }
+    };
+    // the policy is uniform over the launch: one scalar branch around the nine stores
+    if (c.nt) put(std::integral_constant<int, kStoreNT>{});
+    else put(std::integral_constant<int, 0>{});
 }
 
 // Store the 9 post-collision populations of a set at node index o.
@@ -1351,7 +1373,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             store9<SET_Q, S>(c, dst, o, qq);
         }
         if (REFS) {
-            ref_st(rdst, o, (float)nbf, (float)nbq, (float)nbp, (float)nbt);
+            ref_st(rdst, o, (float)nbf, (float)nbq, (float)nbp, (float)nbt, sizeof(S) == 2 && c.nt);
         }
     }
 }

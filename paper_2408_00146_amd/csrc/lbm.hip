@@ -294,7 +294,7 @@ __device__ double src_pop(const CaseDev& cd, const StateSrc& s, int set, int a, 
 // back by y itself through the wall rule of direction abar, so its value is
 // the inverse of that bounce-back / anti-bounce-back.  Reduced-precision
 // storage is relative to the slot node's own references: the FP16-rounded
-// phi, psi, p* and T of the state at y (written to the reference planes).
+// phi, psi, p* and T of the state at y (written to its reference record).
 template <typename S, typename R>
 __device__ void store_node(const CaseDev& cd, const StateSrc& s, int b, int y0x, int y0y)
 {

@@ -213,8 +213,8 @@ def srf_channel(M1: float = 0.0, M2: float = 5.0, beta: float = 0.0, psi_L: floa
     Domain L x H with H = L/2; no-slip walls at x = -1/2 (hot, T_H = 1, psi_L)
     and x = L - 1/2 (cold, T_C = 0, psi_R), periodic in y; T and psi start
     linear between the walls, T_ref = 0.5 at mid-channel.  Bubble of diameter
-    D = D_over_H H at (x0_over_L L, H/2), started at the Laplace pressure of
-    its surface tension there.  Printed (additive) sigma law with
+    D = D_over_H H at (x0_over_L L, H/2), started at the Laplace pressure
+    sigma0/R of the reference surface tension.  Printed (additive) sigma law with
     sigma_T = M1 sigma0 / dT and sigma_TT = M2 sigma0 / dT^2 (dT = 1).
     Velocity scale U_o = (sigma0/mu_A)(R/L)|M1 + M2| (Sec. 6); Re = U_o R/nu_A
     and Ma = U_o R/alpha_A (Sec. 2.1) fix nu_A and alpha_A (rho_A = 1);
@@ -233,9 +233,6 @@ def srf_channel(M1: float = 0.0, M2: float = 5.0, beta: float = 0.0, psi_L: floa
     nu_B = nu_A / mu_ratio / rho_B
     T_of = lambda x: 1.0 - (x + 0.5) / L
     xb, yb = x0_over_L * L - 0.5, 0.5 * H - 0.5
-    psi_b = psi_L + (psi_R - psi_L) * (xb + 0.5) / L
-    sig_b = sigma0 + sigma0 * beta * (T_of(xb) / 0.5) * np.log(1.0 - psi_b) + sT * (T_of(xb) - 0.5) \
-        + sTT * (T_of(xb) - 0.5) ** 2
     s_lam, w_lam = surfactant_ratios(W, Pi, Ex)
     return base(nx=L, ny=H, precision=precision, wall=[1, 1, 0, 0], t_bc=[1, 1, 0, 0], psi_bc=[1, 1, 0, 0],
                 psi_w=[psi_L, psi_R, 0.0, 0.0], T0=T_of(0.0), gradT=-dT / L, xT0=0.0,
@@ -243,7 +240,7 @@ def srf_channel(M1: float = 0.0, M2: float = 5.0, beta: float = 0.0, psi_L: floa
                 psi_inf=1.0, rho_A=1.0, rho_B=rho_B, nu_A=nu_A, nu_B=nu_B, alpha_A=alpha, alpha_B=alpha,
                 D_psi=M_psi, M_phi=M_phi, W=W, s_lam=s_lam, w_lam=w_lam, xc=xb, yc=yb, R=R,
                 psi_bulk=psi_L + (psi_R - psi_L) * 0.5 / L, psi_gradx=(psi_R - psi_L) / L, psi_band=0.0,
-                phi_noise=0.0, p_jump=sig_b / R)
+                phi_noise=0.0, p_jump=sigma0 / R)
 
 
 def srf_scales(p: dict) -> dict:

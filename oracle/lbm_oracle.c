@@ -737,6 +737,13 @@ static void stream(orc_state* s)
         }
 }
 
+void orc_stream_only(orc_state* s, const double* post, double* out)
+{
+    memcpy(s->post, post, 36 * s->n * sizeof(double));
+    stream(s);
+    memcpy(out, s->pop, 36 * s->n * sizeof(double));
+}
+
 void orc_step(orc_state* s, int64_t nsteps)
 {
     for (int64_t t = 0; t < nsteps; ++t) {

@@ -83,6 +83,10 @@ void orc_collide_g(const double g[9], double p, double rho, double ux, double uy
  * equilibrium (jx, jy), first-order relaxation rate omega1, all higher rates 1. */
 void orc_collide_ad(const double pop[9], double X, double jx, double jy, double omega1,
                     double ux, double uy, double out[9]);
+/* Streaming alone: take `post` ([4][9][ny][nx]) as the post-collision
+ * populations, stream them with the wall rules, and write the result to
+ * `out`; the state's populations become that result. */
+void orc_stream_only(orc_state* s, const double* post, double* out);
 /* k-th output (k = 0, 1, ...) of the splitmix64 generator seeded with `seed`
  * (the noise source of the initial phase field). */
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k);

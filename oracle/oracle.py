@@ -100,6 +100,7 @@ def lib():
         L.orc_source_g.argtypes = [C.c_double] * 6 + [dp]
         L.orc_collide_g.argtypes = [dp] + [C.c_double] * 9 + [dp]
         L.orc_collide_ad.argtypes = [dp] + [C.c_double] * 6 + [dp]
+        L.orc_stream_only.argtypes = [C.c_void_p, dp, dp]
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_grad_periodic.argtypes = [dp, C.c_int32, C.c_int32, dp, dp]
@@ -159,6 +160,13 @@ class Oracle:
 
     def set_populations(self, pops: np.ndarray):
         lib().orc_set_populations(self._h, np.ascontiguousarray(pops, dtype=np.float64))
+
+    def stream_only(self, post: np.ndarray) -> np.ndarray:
+        """Stream given post-collision populations [4][9][ny][nx] with the
+        wall rules; returns the streamed populations."""
+        out = np.empty((4, 9, self.ny, self.nx))
+        lib().orc_stream_only(self._h, np.ascontiguousarray(post, dtype=np.float64), out)
+        return out
 
     def diag(self) -> dict:
         out = np.empty(NDIAG)

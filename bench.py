@@ -74,7 +74,7 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(workload: str, config: str) -> int | None:
     """HBM bytes per step launch from the committed counter summary of this
-    workload and kernel configuration ("tile 64x8", "strip 62x16"), or None
+    workload and kernel configuration ("tile 64x4", "walk 64x4"), or None
     when there is none or the kernel sources have changed since the counters
     were taken."""
     path = os.path.join(ROOT, "profiles", f"k_step_{workload}_{config.replace(' ', '')}_hbm_traffic.md")
@@ -226,7 +226,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.workload, f"{kind} {shape[0]}x{shape[1]}"),
-                     "kernel": "k_strip" if kind == "strip" else "k_step", "avg_launch_ms": round(kms, 5),
+                     "kernel": "k_step" if kind == "tile" else "k_walk", "avg_launch_ms": round(kms, 5),
                      "launches": nlaunch, "kernel_only_ms": round(kms_only, 5),
                      "alg_bytes_per_launch": alg_bytes},
     }

@@ -17,41 +17,50 @@
 
 namespace lbm {
 
-// Tile shapes compiled into the library (BX x BY nodes per 256-thread workgroup;
-// with 256 nodes, one node per thread, whose populations stay in registers
-// from the moment pass to the collision).
+// Tile shapes compiled into the library (BX x BY nodes per 256-thread
+// workgroup).  64 x 4: one node per thread, whose populations stay in
+// registers from the moment pass to the collision; 64 x 8: two nodes per
+// thread, each set pulled again right before its collision (the shape of the
+// field-export kernel, kept as a step configuration for cross-checks).
 struct Shape {
     int bx, by;
 };
-constexpr Shape kShapes[] = {{64, 8}, {64, 16}, {64, 32}, {32, 32}, {128, 8}, {128, 16}, {64, 4}};
+constexpr Shape kShapes[] = {{64, 8}, {64, 4}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-// Initial configuration: 64 x 4 tiles (register-held populations, wide
-// accesses to the four-set records).
-constexpr int kOwnShape = 6;
+constexpr int kOwnShape = 1;
 static_assert(kShapes[kOwnShape].bx * kShapes[kOwnShape].by == 256, "one node per thread");
 constexpr int kMacroBX = 64, kMacroBY = 8;
-// Strip-marching configurations: kStripBY rows per iteration (64 x kStripBY
-// threads), segments of kStripSY[j] rows.  Cases narrower than kStripMinNx or
-// lower than kStripMinNy (whose strip halos would wrap more than once) are
-// advanced by the tile kernel of shape 0 in the same step.
-constexpr int kStripBY = 4;
-struct StripCfg {
-    int sy;    // segment rows
-    bool reg;  // populations kept in registers between pull and collision
+
+// Step configurations.  kind 0 (tile): one workgroup per tile of the table.
+// kind 1 (walk): a grid of as many workgroups as the GPU holds at once, each
+// walking its share of the tile table; with `pf` a workgroup issues the
+// own-node loads of its next tile as soon as the current tile's are decoded,
+// so they are in flight while the current tile computes.
+enum { KIND_TILE = 0, KIND_WALK = 1 };
+struct Config {
+    int kind, shape;
+    bool pf;
 };
-constexpr StripCfg kStripCfg[] = {{16, false}, {24, false}, {32, false}, {48, false}, {64, false},
-                                  {16, true},  {24, true},  {32, true},  {48, true},  {64, true}};
-constexpr int kNumStrip = sizeof(kStripCfg) / sizeof(kStripCfg[0]);
-constexpr int kNumConfigs = kNumShapes + kNumStrip;
-constexpr int kStripMinNx = kStripW + 8, kStripMinNy = 16;
+constexpr Config kConfigs[] = {{KIND_TILE, 0, false}, {KIND_TILE, 1, false}, {KIND_WALK, 1, false},
+                               {KIND_WALK, 1, true}};
+constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
+constexpr int kDefaultConfig = 1;
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
-// Remap so that each XCD walks one contiguous band of the tile table: the
-// halo rows shared by vertically adjacent tiles then hit that XCD's own L2.
-__device__ __forceinline__ int xcd_remap(int b, int n)
+// Each XCD works through one contiguous band of the tile table: the halo
+// rows shared by vertically adjacent tiles then hit that XCD's own L2.
+struct Band {
+    int begin, end;   // tiles of this XCD's band
+    int first, step;  // this workgroup's first tile and stride within it
+};
+__device__ __forceinline__ Band xcd_band(int b, int nblocks, int ntiles)
 {
-    const int q = n >> 3, r = n & 7, xcd = b & 7, slot = b >> 3;
-    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    const int xcd = b & 7, slot = b >> 3;
+    const int q = ntiles >> 3, r = ntiles & 7;
+    const int begin = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    const int len = q + (xcd < r ? 1 : 0);
+    const int gq = nblocks >> 3, gr = nblocks & 7;
+    return Band{begin, begin + len, begin + slot, gq + (xcd < gr ? 1 : 0)};
 }
 
 // A tile whose 3-node halo lies inside the lattice needs no wrap or wall logic.
@@ -60,83 +69,143 @@ __device__ __forceinline__ bool interior(const CaseDev& cd, int x0, int y0, int 
     return x0 >= 3 && y0 >= 3 && x0 + bx + 3 <= cd.nx && y0 + by + 3 <= cd.ny;
 }
 
-template <typename R, typename S, int BX, int BY, int MODE>
+// Lattice geometry of a case (what the pull addressing needs).
+struct Geo {
+    int nx, ny, pitch, plane, wallx, wally;
+    __device__ explicit Geo(const CaseDev& c)
+        : nx(c.nx), ny(c.ny), pitch(c.pitch), plane((int)c.plane), wallx(c.wallx), wally(c.wally)
+    {
+    }
+};
+
+template <typename R, typename S, int BX, int BY, int MODE, bool PRE = false, typename NEXT = NoNext>
 __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int x0, int y0, int b, Smem<R, BX, BY, sizeof(R) == 4>& sh,
-                                         const MacroOut& mo, double* dacc)
+                                         const MacroOut& mo, double* dacc, Raw4<S>* pre = nullptr,
+                                         const NEXT& next = NEXT{})
 {
     const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
     const View dst{make_rsrc(cd.buf[b ^ 1], MODE == MODE_STEP ? cd.pop_bytes : 0u)};
     const Rsrc rsrc = make_rsrc(cd.rbuf[b], cd.ref_bytes);
     const Rsrc rdst = make_rsrc(cd.rbuf[b ^ 1], MODE == MODE_STEP ? cd.ref_bytes : 0u);
     if (interior(cd, x0, y0, BX, BY))
-        tile_body<R, S, BX, BY, MODE, true>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
+        tile_body<R, S, BX, BY, MODE, true, PRE>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc, pre, next);
     else
-        tile_body<R, S, BX, BY, MODE, false>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
+        tile_body<R, S, BX, BY, MODE, false, PRE>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc, pre, next);
 }
 
 // Storage selection of a step launch: one storage type per kernel keeps the
 // code of a single tile body in the instruction cache.  A handle that mixes
-// FP32 and FP16 cases launches the FP16 and the FP32 tile kernels over the two
-// parts of its tile table; the kernel that branches per tile serves the tiles
-// that strip configurations leave to the tile kernel.
-enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_MIXED = 3 };
+// FP32 and FP16 cases launches the FP16 and the FP32 kernels over the two
+// parts of its tile table.
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 
-template <int ST, int BX, int BY>
+template <int ST>
+using RealOf = typename std::conditional<ST == ST_F64, double, float>::type;
+template <int ST>
+using StoreOf = typename std::conditional<ST == ST_F64, double, typename std::conditional<ST == ST_F32, float, __half>::type>::type;
+
 // Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the 64 x 4
-// FP16-storage tiles, three (<= 168) for the other FP32/FP16 and mixed tiles
-// (the FP32 and mixed 64 x 4 tiles would spill at 128) and the FP64 64 x 4
-// tile, two for the larger FP64 tiles.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? (BX * BY == 256 ? 3 : 2) : (BX * BY == 256 && ST == ST_F16 ? 4 : 3)))) void k_step(const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles,
-                                              int ntiles, const int64_t* __restrict__ steps, int t)
+// FP16-storage tiles, three (<= 168) for the FP32 64 x 4 tiles (they would
+// spill at 128), the FP64 64 x 4 tiles and every tile that carries prefetched
+// loads, two for FP64 64 x 8.
+constexpr int waves_of(int st, int bx, int by, bool pf)
 {
-    using R = typename std::conditional<ST == ST_F64, double, float>::type;
-    __shared__ Smem<R, BX, BY, sizeof(R) == 4> sh;
-    const TileRec tr = tiles[xcd_remap(blockIdx.x, ntiles)];
+    return st == ST_F64 ? (bx * by == 256 ? 3 : 2) : (bx * by == 256 && !pf ? 4 : 3);
+}
+
+// The step's budget check: a case stops at its max_steps.
+__device__ __forceinline__ bool tile_live(const CaseDev* cases, const TileRec& tr, const int64_t* steps, int t, int& b)
+{
     const CaseDev& cd = cases[tr.c];
     const int64_t s = steps[tr.c] + t;
-    if (cd.max_steps > 0 && s >= cd.max_steps) return;  // uniform over the block
+    b = (int)(s & 1);
+    return !(cd.max_steps > 0 && s >= cd.max_steps);
+}
+
+// One workgroup per tile of the table.
+template <int ST, int BX, int BY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST, BX, BY, false)))) void k_step(
+    const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles, int ntiles, const int64_t* __restrict__ steps,
+    int t)
+{
+    using R = RealOf<ST>;
+    using S = StoreOf<ST>;
+    __shared__ Smem<R, BX, BY, sizeof(R) == 4> sh;
+    const Band bd = xcd_band(blockIdx.x, gridDim.x, ntiles);
+    const TileRec tr = tiles[bd.first];
+    int b;
+    if (!tile_live(cases, tr, steps, t, b)) return;  // uniform over the block
+    const CaseDev& cd = cases[tr.c];
     Ctx<R> c;
     c.load(cd);
     const MacroOut mo{nullptr, 0u, nullptr};
-    const int b = (int)(s & 1);
-    if constexpr (ST == ST_F64) {
-        run_tile<double, double, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
-    } else if constexpr (ST == ST_F32) {
-        run_tile<float, float, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
-    } else if constexpr (ST == ST_F16) {
-        run_tile<float, __half, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
-    } else {
-        if (cd.prec == PREC_FP16S) run_tile<float, __half, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
-        else run_tile<float, float, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+    run_tile<R, S, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+}
+
+// Issue the own-node loads of thread threadIdx.x in tile k (64 x 4).
+template <typename S>
+__device__ __forceinline__ void issue_own(const CaseDev* cases, const TileRec* tiles, const int64_t* steps, int t, int k,
+                                          Raw4<S> q[9])
+{
+    const TileRec tr = tiles[k];
+    int b;
+    (void)tile_live(cases, tr, steps, t, b);
+    const CaseDev& cd = cases[tr.c];
+    const Geo g(cd);
+    const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
+    int mx, my, tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (interior(cd, tr.x0, tr.y0, 64, 4)) {
+        (void)own_node<64>(g, tr.x0, tr.y0, tid, true, mx, my);
+        raw36<true, true, S>(g, src, mx, my, q);
+    } else if (own_node<64>(g, tr.x0, tr.y0, tid, false, mx, my)) {
+        raw36<false, true, S>(g, src, mx, my, q);
     }
 }
 
-template <int ST, int BY, bool REG>
-__global__ __launch_bounds__(64 * BY) void k_strip(const CaseDev* __restrict__ cases, const StripRec* __restrict__ units,
-                                                   int nunits, const int64_t* __restrict__ steps, int t)
+// A grid of resident workgroups walking the 64 x 4 tile table: workgroup b
+// takes tiles first, first + step, ... of its XCD's band (tiles of cases
+// whose step budget is spent are skipped).  PF: the next tile's own-node
+// loads are issued while the current tile computes.
+template <int ST, bool PF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST, 64, 4, PF)))) void k_walk(
+    const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles, int ntiles, const int64_t* __restrict__ steps,
+    int t)
 {
-    using R = typename std::conditional<ST == ST_F64, double, float>::type;
-    __shared__ StripSmem<R, BY, sizeof(R) == 4> sh;
-    const StripRec u = units[xcd_remap(blockIdx.x, nunits)];
-    const CaseDev& cd = cases[u.c];
-    const int64_t s = steps[u.c] + t;
-    if (cd.max_steps > 0 && s >= cd.max_steps) return;  // uniform over the block
-    Ctx<R> c;
-    c.load(cd);
-    const int b = (int)(s & 1);
-    const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
-    const View dst{make_rsrc(cd.buf[b ^ 1], cd.pop_bytes)};
-    const Rsrc rsrc = make_rsrc(cd.rbuf[b], cd.ref_bytes);
-    const Rsrc rdst = make_rsrc(cd.rbuf[b ^ 1], cd.ref_bytes);
-    if constexpr (ST == ST_F64) {
-        strip_body<double, double, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
-    } else if constexpr (ST == ST_F32) {
-        strip_body<float, float, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
-    } else if constexpr (ST == ST_F16) {
-        strip_body<float, __half, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
-    } else {
-        if (cd.prec == PREC_FP16S) strip_body<float, __half, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
-        else strip_body<float, float, BY, REG>(c, u, src, dst, rsrc, rdst, sh);
+    using R = RealOf<ST>;
+    using S = StoreOf<ST>;
+    constexpr int BX = 64, BY = 4;
+    __shared__ Smem<R, BX, BY, sizeof(R) == 4> sh;
+    const Band bd = xcd_band(blockIdx.x, gridDim.x, ntiles);
+    // first live tile at or after k on this workgroup's stride
+    auto next_live = [&](int k) {
+        int b;
+        while (k < bd.end && !tile_live(cases, tiles[k], steps, t, b)) k += bd.step;
+        return k;
+    };
+    int k = next_live(bd.first);
+    Raw4<S> pre[9];
+    if (PF && k < bd.end) issue_own<S>(cases, tiles, steps, t, k, pre);
+    const MacroOut mo{nullptr, 0u, nullptr};
+    while (k < bd.end) {
+        const int kn = next_live(k + bd.step);
+        const TileRec tr = tiles[k];
+        int b;
+        (void)tile_live(cases, tr, steps, t, b);
+        const CaseDev& cd = cases[tr.c];
+        Ctx<R> c;
+        c.load(cd);
+        if constexpr (PF) {
+            auto nxt = [&](Raw4<S>* q) {
+                if (kn < bd.end) issue_own<S>(cases, tiles, steps, t, kn, q);
+            };
+            run_tile<R, S, BX, BY, MODE_STEP, true>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr, pre, nxt);
+        } else {
+            run_tile<R, S, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+        }
+        k = kn;
+        // the next tile's LDS writes must not overtake this tile's last reads
+        if (k < bd.end) __syncthreads();
     }
 }
 
@@ -454,14 +523,9 @@ size_t case_ref_bytes(const lbm_case& c) { return c.precision == LBM_FP64 ? 0 : 
 
 int64_t tiles_of(const lbm_case& c, int bx, int by) { return (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by); }
 
-bool strip_ok(const lbm_case& c) { return c.nx >= kStripMinNx && c.ny >= kStripMinNy; }
-
-int64_t strips_of(const lbm_case& c, int sy) { return strip_ok(c) ? (int64_t)((c.nx + kStripW - 1) / kStripW) * ((c.ny + sy - 1) / sy) : 0; }
-
 struct Layout {
-    size_t off_cases, off_steps, off_partials, off_diag, off_tiles[kNumShapes], off_strips[kNumStrip], off_rest, off_mtiles,
-        off_pops, total;
-    int64_t ntiles[kNumShapes], ntiles16[kNumShapes], nstrips[kNumStrip], nrest, nmtiles, max_case_mtiles;
+    size_t off_cases, off_steps, off_partials, off_diag, off_tiles[kNumShapes], off_mtiles, off_pops, total;
+    int64_t ntiles[kNumShapes], ntiles16[kNumShapes], nmtiles, max_case_mtiles;
 };
 
 Layout layout_of(const lbm_case* cs, int n)
@@ -494,21 +558,6 @@ Layout layout_of(const lbm_case* cs, int n)
         L.ntiles[s] = t;
         L.ntiles16[s] = t16;
         L.off_tiles[s] = o;
-        o = align256(o + sizeof(TileRec) * (size_t)t);
-    }
-    for (int j = 0; j < kNumStrip; ++j) {
-        int64_t t = 0;
-        for (int i = 0; i < n; ++i) t += strips_of(cs[i], kStripCfg[j].sy);
-        L.nstrips[j] = t;
-        L.off_strips[j] = o;
-        o = align256(o + sizeof(StripRec) * (size_t)t);
-    }
-    {
-        int64_t t = 0;
-        for (int i = 0; i < n; ++i)
-            if (!strip_ok(cs[i])) t += tiles_of(cs[i], kShapes[0].bx, kShapes[0].by);
-        L.nrest = t;
-        L.off_rest = o;
         o = align256(o + sizeof(TileRec) * (size_t)t);
     }
     L.off_mtiles = o;
@@ -623,46 +672,25 @@ InitDev make_init(const lbm_case& c)
 using StepKernel = void (*)(const CaseDev*, const TileRec*, int, const int64_t*, int);
 
 template <int ST>
-StepKernel step_kernel_st(int shape)
+StepKernel step_kernel_st(const Config& cf)
 {
-    switch (shape) {
-        case 0: return k_step<ST, 64, 8>;
-        case 1: return k_step<ST, 64, 16>;
-        case 2: return k_step<ST, 64, 32>;
-        case 3: return k_step<ST, 32, 32>;
-        case 4: return k_step<ST, 128, 8>;
-        case 5: return k_step<ST, 128, 16>;
-        case 6: return k_step<ST, 64, 4>;
+    if (cf.kind == KIND_WALK) {
+        if constexpr (ST == ST_F64) return k_walk<ST, false>;  // no prefetching FP64 walk (see config_ok)
+        else return cf.pf ? k_walk<ST, true> : k_walk<ST, false>;
     }
-    return nullptr;
+    return cf.shape == 0 ? k_step<ST, 64, 8> : k_step<ST, 64, 4>;
 }
 
-StepKernel step_kernel(int st, int shape)
+StepKernel step_kernel(int st, const Config& cf)
 {
     switch (st) {
-        case ST_F64: return step_kernel_st<ST_F64>(shape);
-        case ST_F32: return step_kernel_st<ST_F32>(shape);
-        case ST_F16: return step_kernel_st<ST_F16>(shape);
+        case ST_F64: return step_kernel_st<ST_F64>(cf);
+        case ST_F16: return step_kernel_st<ST_F16>(cf);
     }
-    return step_kernel_st<ST_MIXED>(shape);
+    return step_kernel_st<ST_F32>(cf);
 }
 
-using StripKernel = void (*)(const CaseDev*, const StripRec*, int, const int64_t*, int);
-
-template <bool REG>
-StripKernel strip_kernel_reg(int st)
-{
-    switch (st) {
-        case ST_F64: return k_strip<ST_F64, kStripBY, REG>;
-        case ST_F32: return k_strip<ST_F32, kStripBY, REG>;
-        case ST_F16: return k_strip<ST_F16, kStripBY, REG>;
-    }
-    return k_strip<ST_MIXED, kStripBY, REG>;
-}
-
-StripKernel strip_kernel(int st, bool reg) { return reg ? strip_kernel_reg<true>(st) : strip_kernel_reg<false>(st); }
-
-// Tiles must fit the 64 KiB per-workgroup LDS budget (two workgroups per CU).
+// Tiles must fit the 64 KiB per-workgroup LDS budget.
 bool shape_ok(int shape, bool fp64)
 {
     const int bx = kShapes[shape].bx, by = kShapes[shape].by;
@@ -671,11 +699,27 @@ bool shape_ok(int shape, bool fp64)
     return lds <= 65536;
 }
 
-// Step configuration: tile shape (index < kNumShapes) or strip segment length.
+// Prefetching walks carry 36 extra registers per thread; FP64 tiles have no room for them.
 bool config_ok(int cfg, bool fp64)
 {
     if (cfg < 0 || cfg >= kNumConfigs) return false;
-    return cfg >= kNumShapes || shape_ok(cfg, fp64);
+    if (fp64 && kConfigs[cfg].pf) return false;
+    return shape_ok(kConfigs[cfg].shape, fp64);
+}
+
+// Workgroups of a kernel resident on the whole GPU at once (its occupancy
+// times the compute units), cached per kernel.
+int resident_blocks(StepKernel k)
+{
+    static std::map<const void*, int> cache;
+    auto it = cache.find((const void*)k);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k, 256, 0) != hipSuccess || cus <= 0 || per <= 0)
+        return 0;
+    cache[(const void*)k] = cus * per;
+    return cus * per;
 }
 
 }  // namespace
@@ -690,8 +734,8 @@ struct lbm_handle {
     char* ws = nullptr;
     Layout L{};
     bool fp64 = false;
-    int st = ST_F32;  // storage class of the step kernel
-    int shape = 1;
+    int st = ST_F32;  // ST_F64, or ST_F32 for FP32 / FP16-storage handles (one kernel per storage type)
+    int cfg = kDefaultConfig;  // step configuration (index into kConfigs)
     bool use_graph = true;
     int timing = 0;  // 0 off, 1 per-step eager launches, 2 per launched chunk
     std::map<int, hipGraphExec_t> graphs;
@@ -705,42 +749,32 @@ struct lbm_handle {
     TileRec* d_tiles(int s) { return (TileRec*)(ws + L.off_tiles[s]); }
     TileRec* d_mtiles() { return (TileRec*)(ws + L.off_mtiles); }
 
-    StripRec* d_strips(int j) { return (StripRec*)(ws + L.off_strips[j]); }
-    TileRec* d_rest() { return (TileRec*)(ws + L.off_rest); }
 
+    // One kernel launch over tiles [t0, t0 + n) of the shape's table.
+    int launch_part(const Config& cf, int st_part, int64_t t0, int64_t n, int t)
+    {
+        if (n <= 0) return LBM_OK;
+        const StepKernel k = step_kernel(st_part, cf);
+        int64_t grid = n;
+        if (cf.kind == KIND_WALK) {
+            const int res = resident_blocks(k);
+            if (res <= 0) return fail(LBM_E_DEVICE, "occupancy query of the walk kernel failed");
+            grid = std::min<int64_t>(n, res);
+        }
+        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, stream, d_cases(), d_tiles(cf.shape) + t0, (int)n,
+                           d_steps(), t);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
     int launch_step(int t)
     {
-        if (shape < kNumShapes) {
-            const int64_t nt = L.ntiles[shape];
-            if (nt <= 0) return LBM_OK;
-            if (st == ST_MIXED) {
-                // FP16-storage tiles, then the FP32 tiles, each with its own kernel
-                const int64_t n16 = L.ntiles16[shape];
-                hipLaunchKernelGGL(step_kernel(ST_F16, shape), dim3((unsigned)n16), dim3(256), 0, stream, d_cases(),
-                                   d_tiles(shape), (int)n16, d_steps(), t);
-                HIPCHK(hipGetLastError());
-                hipLaunchKernelGGL(step_kernel(ST_F32, shape), dim3((unsigned)(nt - n16)), dim3(256), 0, stream,
-                                   d_cases(), d_tiles(shape) + n16, (int)(nt - n16), d_steps(), t);
-                HIPCHK(hipGetLastError());
-                return LBM_OK;
-            }
-            hipLaunchKernelGGL(step_kernel(st, shape), dim3((unsigned)nt), dim3(256), 0, stream, d_cases(),
-                               d_tiles(shape), (int)nt, d_steps(), t);
-            HIPCHK(hipGetLastError());
-            return LBM_OK;
-        }
-        const int j = shape - kNumShapes;
-        if (L.nstrips[j] > 0) {
-            hipLaunchKernelGGL(strip_kernel(st, kStripCfg[j].reg), dim3((unsigned)L.nstrips[j]), dim3(64 * kStripBY), 0, stream,
-                               d_cases(), d_strips(j), (int)L.nstrips[j], d_steps(), t);
-            HIPCHK(hipGetLastError());
-        }
-        if (L.nrest > 0) {
-            hipLaunchKernelGGL(step_kernel(st, 0), dim3((unsigned)L.nrest), dim3(256), 0, stream, d_cases(), d_rest(),
-                               (int)L.nrest, d_steps(), t);
-            HIPCHK(hipGetLastError());
-        }
-        return LBM_OK;
+        const Config& cf = kConfigs[cfg];
+        const int64_t nt = L.ntiles[cf.shape], n16 = L.ntiles16[cf.shape];
+        if (st == ST_F64) return launch_part(cf, ST_F64, 0, nt, t);
+        // FP16-storage tiles first in the table, then the FP32 tiles, each with its own kernel
+        int rc = launch_part(cf, ST_F16, 0, n16, t);
+        if (rc == LBM_OK) rc = launch_part(cf, ST_F32, n16, nt - n16, t);
+        return rc;
     }
     int launch_advance(int64_t k)
     {
@@ -854,12 +888,10 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
     h->L = L;
     h->fp64 = any64;
     {
-        bool a32 = false, a16 = false;
-        for (int i = 0; i < ncases; ++i) (cases[i].precision == LBM_FP16S ? a16 : a32) = true;
-        h->st = any64 ? ST_F64 : (a32 && a16 ? ST_MIXED : (a16 ? ST_F16 : ST_F32));
+        h->st = any64 ? ST_F64 : ST_F32;
     }
     h->steps.assign(ncases, 0);
-    h->shape = kOwnShape;
+    h->cfg = kDefaultConfig;
 
     size_t o = L.off_pops;
     for (int i = 0; i < ncases; ++i) {
@@ -897,27 +929,6 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         for (int i = 0; i < ncases; ++i)
             if (cases[i].precision != LBM_FP16S) add_tiles(i, kShapes[s].bx, kShapes[s].by);
         rc = upload(h->d_tiles(s));
-    }
-    for (int j = 0; j < kNumStrip && rc == LBM_OK; ++j) {
-        std::vector<StripRec> st;
-        for (int i = 0; i < ncases; ++i) {
-            if (!strip_ok(cases[i])) continue;
-            const int sy = kStripCfg[j].sy;
-            for (int y = 0; y < cases[i].ny; y += sy)
-                for (int x = 0; x < cases[i].nx; x += kStripW) st.push_back(StripRec{i, x, y, std::min(y + sy, cases[i].ny)});
-        }
-        if (!st.empty()) {
-            hipError_t e = hipMemcpyAsync(h->d_strips(j), st.data(), st.size() * sizeof(StripRec), hipMemcpyHostToDevice,
-                                          h->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-            if (e != hipSuccess) rc = fail(LBM_E_DEVICE, "strip table upload: %s", hipGetErrorString(e));
-        }
-    }
-    if (rc == LBM_OK) {
-        tiles.clear();
-        for (int i = 0; i < ncases; ++i)
-            if (!strip_ok(cases[i])) add_tiles(i, kShapes[0].bx, kShapes[0].by);
-        rc = upload(h->d_rest());
     }
     if (rc == LBM_OK) {
         tiles.clear();
@@ -1174,39 +1185,38 @@ int lbm_tile_count(void) { return kNumConfigs; }
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by)
 {
     if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    const bool strip = index >= kNumShapes;
-    if (bx) *bx = strip ? kStripW : kShapes[index].bx;
-    if (by) *by = strip ? kStripCfg[index - kNumShapes].sy : kShapes[index].by;
+    if (bx) *bx = kShapes[kConfigs[index].shape].bx;
+    if (by) *by = kShapes[kConfigs[index].shape].by;
     return LBM_OK;
 }
 
 int lbm_tile_kind(int32_t index)
 {
     if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    return index >= kNumShapes ? 1 : 0;
+    return kConfigs[index].kind == KIND_WALK ? (kConfigs[index].pf ? 2 : 1) : 0;
 }
 
 int lbm_set_tile(lbm_handle* h, int32_t index)
 {
     CHECK_H(h);
     if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    if (!config_ok(index, h->fp64)) return fail(LBM_E_INVAL, "tile %d exceeds the LDS budget for FP64", index);
-    if (index != h->shape) h->drop_graphs();
-    h->shape = index;
+    if (!config_ok(index, h->fp64)) return fail(LBM_E_INVAL, "configuration %d is not available for FP64 cases", index);
+    if (index != h->cfg) h->drop_graphs();
+    h->cfg = index;
     return LBM_OK;
 }
 
 int lbm_get_tile(lbm_handle* h)
 {
     CHECK_H(h);
-    return h->shape;
+    return h->cfg;
 }
 
 int lbm_autotune(lbm_handle* h, int32_t trial_steps)
 {
     CHECK_H(h);
     if (trial_steps <= 0) return fail(LBM_E_INVAL, "trial_steps must be > 0");
-    const int keep = h->shape;
+    const int keep = h->cfg;
     int best = keep;
     float best_ms = 1e30f;
     hipEvent_t a, b;
@@ -1215,7 +1225,7 @@ int lbm_autotune(lbm_handle* h, int32_t trial_steps)
     int rc = LBM_OK;
     for (int s = 0; s < kNumConfigs && rc == LBM_OK; ++s) {
         if (!config_ok(s, h->fp64)) continue;
-        h->shape = s;
+        h->cfg = s;
         // t = 0 every time: each trial re-reads the current state and rewrites
         // the scratch half of the ping-pong pair, leaving the state unchanged.
         for (int w = 0; w < 2 && rc == LBM_OK; ++w) rc = h->launch_step(0);
@@ -1236,7 +1246,7 @@ int lbm_autotune(lbm_handle* h, int32_t trial_steps)
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    h->shape = keep;
+    h->cfg = keep;
     if (rc != LBM_OK) return rc;
     return lbm_set_tile(h, best);
 }

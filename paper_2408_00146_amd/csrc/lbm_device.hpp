@@ -371,8 +371,8 @@ struct Nbr {
     bool wxm, wxp, wym, wyp;
 };
 
-template <typename R>
-__device__ __forceinline__ Nbr nbr_of(const Ctx<R>& c, int mx, int my)
+template <typename CT>
+__device__ __forceinline__ Nbr nbr_of(const CT& c, int mx, int my)
 {
     Nbr n;
     const int xl = mx - 1, xr = mx + 1, yd = my - 1, yu = my + 1;
@@ -524,8 +524,8 @@ __device__ __forceinline__ void fix9(const Ctx<R>& c, const S r[9], int ux, int 
 // Loads of the populations pulled to node (mx, my), one wide load per
 // direction: the four sets of a direction share its source slot (and, beyond
 // a wall, its bounce-back slot).  ALL = false loads set f alone.
-template <int A, bool INT, bool ALL, typename S, typename R>
-__device__ __forceinline__ void raw_dir(const Ctx<R>& c, View src, int mx, int my, const Nbr& nb, Raw4<S>* q)
+template <int A, bool INT, bool ALL, typename S, typename CT>
+__device__ __forceinline__ void raw_dir(const CT& c, View src, int mx, int my, const Nbr& nb, Raw4<S>* q)
 {
     constexpr int EX = ex(A), EY = ey(A);
     constexpr uint32_t E4 = 4u * sizeof(S);
@@ -547,19 +547,19 @@ __device__ __forceinline__ void raw_dir(const Ctx<R>& c, View src, int mx, int m
     else q[A].ld1(src.r, v, so);
 }
 
-template <bool INT, bool ALL, typename S, typename R>
-__device__ __forceinline__ void raw36(const Ctx<R>& c, View src, int mx, int my, Raw4<S> q[9])
+template <bool INT, bool ALL, typename S, typename CT>
+__device__ __forceinline__ void raw36(const CT& c, View src, int mx, int my, Raw4<S> q[9])
 {
     const Nbr nb = INT ? Nbr{} : nbr_of(c, mx, my);
-    raw_dir<0, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<1, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<2, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<3, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<4, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<5, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<6, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<7, INT, ALL, S, R>(c, src, mx, my, nb, q);
-    raw_dir<8, INT, ALL, S, R>(c, src, mx, my, nb, q);
+    raw_dir<0, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<1, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<2, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<3, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<4, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<5, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<6, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<7, INT, ALL, S>(c, src, mx, my, nb, q);
+    raw_dir<8, INT, ALL, S>(c, src, mx, my, nb, q);
 }
 
 // fix9 of set SET from the wide-loaded records.
@@ -885,13 +885,47 @@ __device__ __forceinline__ void grad2(const T* D, const T* B, int p, int W, T& g
     gy = dy * T(1.0 / 12.0);
 }
 
-template <typename R, typename S, int BX, int BY, int MODE, bool INT>
+// Lattice node of the own slot of thread tid in the tile at (x0, y0): the
+// node at unwrapped coordinates (x0 + tid % BX, y0 + tid / BX), wrapped once
+// along a periodic axis.  False when the slot lies beyond a wall or beyond one
+// wrap (no live node reads it).  An own slot past the lattice edge of a
+// periodic axis holds the wrapped node: the halo of the live nodes there.
+template <int BX, typename CT>
+__device__ __forceinline__ bool own_node(const CT& c, int x0, int y0, int tid, bool intr, int& mx, int& my)
+{
+    const int ux = x0 + tid % BX, uy = y0 + tid / BX;
+    if (intr) {
+        mx = ux;
+        my = uy;
+        return true;
+    }
+    mx = c.wallx ? ux : (ux >= c.nx ? ux - c.nx : ux);
+    my = c.wally ? uy : (uy >= c.ny ? uy - c.ny : uy);
+    return mx < c.nx && my < c.ny;
+}
+
+// No loads to issue for a following tile.
+struct NoNext {
+    template <typename Q>
+    __device__ __forceinline__ void operator()(Q*) const
+    {
+    }
+};
+
+// One step of one tile.  PRE: the own-node records of thread tid (one own
+// node per thread, 64 x 4 tiles) were loaded into `pre` before the call;
+// `next(pre)` is called as soon as they are decoded, so that loads for a
+// following tile can be issued into the same registers and stay in flight
+// while this tile computes.
+template <typename R, typename S, int BX, int BY, int MODE, bool INT, bool PRE = false, typename NEXT = NoNext>
 __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View src, View dst, Rsrc rsrc, Rsrc rdst,
-                                          Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc)
+                                          Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc,
+                                          Raw4<S>* pre = nullptr, const NEXT& next = NEXT{})
 {
     constexpr bool REFS = sizeof(R) == 4;
     constexpr int NT = 256;
     constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
+    static_assert(!PRE || OWN1, "preloaded own-node records need one own node per thread");
     // population loads of phase 1a issued before the storage references are
     // committed (one own node per thread; interior tiles, and with FP16
     // storage boundary tiles too).  FP64, and FP32 boundary tiles, keep the
@@ -899,6 +933,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr bool EARLY = OWN1 && (sizeof(S) == 2 || (INT && sizeof(S) == 4));
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
+    // opaque from the start: inside a loop over tiles nothing derived from the
+    // thread index alone is hoisted out and kept live across tiles
+    asm volatile("" : "+v"(tid));
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
 
     // per-node references of the f and q sets at unwrapped tile coordinates
@@ -1017,14 +1054,17 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             my = wrapy(uy);
             return !(ghostx(ux) || ghosty(uy) || (!INT && (mx < 0 || mx >= c.nx || my < 0 || my >= c.ny)));
         };
-        int ux, uy, mx, my, alx, aly, aux, auy, amx, amy, blx, bly, bux, buy, bmx, bmy;
+        int mx, my, alx, aly, aux, auy, amx, amy, blx, bly, bux, buy, bmx, bmy;
         const int olx = tid % BX + 2, oly = tid / BX + 2;
-        const bool own_ok = node_of(olx, oly, ux, uy, mx, my);
+        const int ux = x0 + tid % BX, uy = y0 + tid / BX;
+        const bool own_ok = own_node<BX>(c, x0, y0, tid, INT, mx, my);
         ring_slot(tid, alx, aly);
         const bool a_ok = node_of(alx, aly, aux, auy, amx, amy), a_e1 = tid < NR1;
         const bool b_has = tid + NT < NR;
         ring_slot(b_has ? tid + NT : NR - 1, blx, bly);
-        const bool b_ok = b_has && node_of(blx, bly, bux, buy, bmx, bmy);
+        // coordinates set on every thread (the reference read below is unconditional)
+        const bool b_in = node_of(blx, bly, bux, buy, bmx, bmy);
+        const bool b_ok = b_has && b_in;
         // sums and LDS writes
         auto put_f = [&](int lx, int ly, R base, const R* v) {
             const int k = ly * W2 + lx;
@@ -1040,11 +1080,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         };
         if constexpr (EARLY) {
             // loads, then the references, then the decoding
-            Raw4<S> qO[9], qA[9], qB[9];
-            if (own_ok) raw36<INT, true, S, R>(c, src, mx, my, qO);
-            if (a_ok && a_e1) raw36<INT, true, S, R>(c, src, amx, amy, qA);
-            else if (a_ok) raw36<INT, false, S, R>(c, src, amx, amy, qA);
-            if (b_ok) raw36<INT, false, S, R>(c, src, bmx, bmy, qB);
+            Raw4<S> qO_own[9], qA[9], qB[9];
+            Raw4<S>* qO = PRE ? pre : qO_own;
+            if (own_ok && !PRE) raw36<INT, true, S>(c, src, mx, my, qO);
+            if (a_ok && a_e1) raw36<INT, true, S>(c, src, amx, amy, qA);
+            else if (a_ok) raw36<INT, false, S>(c, src, amx, amy, qA);
+            if (b_ok) raw36<INT, false, S>(c, src, bmx, bmy, qB);
             if (REFS) ref_commit();
             // ring slots first (their values die in the sums), the own node last
             {
@@ -1077,6 +1118,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, bp, bh, bq, G, H, Q);
             }
+            if (PRE) next(pre);
         } else {
             // ring slots first, then the own node (fewer values live at once)
             {
@@ -1085,7 +1127,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 R VA[9], VG[9], VH[9], VQ[9], VB[9];
                 if (a_ok && a_e1) {
                     Raw4<S> qA[9];
-                    raw36<INT, true, S, R>(c, src, amx, amy, qA);
+                    raw36<INT, true, S>(c, src, amx, amy, qA);
                     fix9q<SET_F, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abf, ref_f, VA);
                     fix9q<SET_G, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abp, ref_p, VG);
                     fix9q<SET_H, INT, REFS, S, R>(c, qA, aux, auy, amx, amy, abh, ref_t, VH);
@@ -1104,8 +1146,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = ref_t(ux, uy);
             if (own_ok) {
-                Raw4<S> qO[9];
-                raw36<INT, true, S, R>(c, src, mx, my, qO);
+                Raw4<S> qO_own[9];
+                Raw4<S>* qO = PRE ? pre : qO_own;
+                if (!PRE) raw36<INT, true, S>(c, src, mx, my, qO);
                 fix9q<SET_F, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bf, ref_f, F);
                 fix9q<SET_G, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bp, ref_p, G);
                 fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, ref_t, H);
@@ -1113,6 +1156,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, bp, bh, bq, G, H, Q);
             }
+            if (PRE) next(pre);
         }
     } else {
         // E1 slots (all four sets, their 36 loads issued together), then the
@@ -1375,484 +1419,6 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         if (REFS) {
             ref_st(rdst, o, (float)nbf, (float)nbq, (float)nbp, (float)nbt, sizeof(S) == 2 && c.nt);
         }
-    }
-}
-
-// ------------------------------------------------------------ strip marching
-// A workgroup of 64 x BY threads owns a strip of kStripW = 62 columns and a
-// segment [y0, y1) of rows, and marches up the segment BY rows per
-// iteration.  The reduced fields (phi; p*, T, psi; normal, sigma; storage
-// references) of the rows still needed live in LDS ring buffers (row r in
-// slot r mod RING), so each population is pulled about once per step
-// instead of once per overlapping tile halo, and each node keeps its 36
-// pulled populations in registers from the pull to its collision.
-// Wave j handles row y + j; lane l covers column x0 - 1 + l: lanes 1..62
-// own a node, lanes 0 and 63 compute the one-node x halo of the moments.
-// Per iteration (base row y):
-//   B  pull rows y .. y+BY-1 (registers; phi of rows >= y+2 and p*, T, psi
-//      of rows >= y+1 into the rings) and the halo slots: phi of rows
-//      y+BY, y+BY+1 and of the 2-node x halo, p*, T, psi of row y+BY;
-//   B2 (strips touching a wall) ghost nodes from their mirror nodes;
-//   C  normal and sigma of rows y+1 .. y+BY; storage references of the next
-//      iteration's rows;
-//   D  collide rows y .. y+BY-1 and store.
-// With RING >= 2 BY + 4 the writes of B and C never touch rows that the
-// previous D still reads, so an iteration needs two barriers.
-struct StripRec {
-    int32_t c, x0, y0, y1;
-};
-
-constexpr int kStripW = 62;
-
-template <typename R, int BY, bool REFS>
-struct StripSmem {
-    // rows in flight: references and phi y-1 .. y+2BY+2, p*/T/psi y-1 .. y+2BY;
-    // normals and sigma are written (stage C) only after the previous
-    // collision has finished, so they need 2 BY rows
-    static constexpr int RING = 4 * BY, RING1 = 2 * BY;
-    static constexpr int W3 = kStripW + 6, W2 = kStripW + 4, W1 = kStripW + 2;
-    R rf[REFS ? RING * W3 : 1];  // phi reference
-    R rq[REFS ? RING * W3 : 1];  // psi reference
-    R rp[REFS ? RING * W3 : 1];  // p* reference
-    R rt[REFS ? RING * W3 : 1];  // T reference
-    R phd[RING * W2];            // phi deviation from its reference
-    R phb[REFS ? RING * W2 : 1];
-    double sg[RING1 * W1];       // sigma (FP64)
-    R ps[RING * W1];             // p* (deviation from its reference with reduced-precision storage)
-    R psb[REFS ? RING * W1 : 1]; // p* reference
-    R ts[RING * W1];             // T - T_w(column)
-    R pq[RING * W1];             // psi
-    R nx[RING1 * W1];
-    R ny[RING1 * W1];
-};
-
-// Isotropic gradient (Sec. 3) on ring rows rm (y-1), r0 (y), rp (y+1) at
-// column cc; same operation order as grad2.
-template <typename R, bool REFS, typename T = R>
-__device__ __forceinline__ void grad_ring(const T* D, const T* B, int rm, int r0, int rp, int cc, T& gx, T& gy)
-{
-    T dx = T(4) * (D[r0 + cc + 1] - D[r0 + cc - 1]) + (D[rp + cc + 1] - D[rp + cc - 1]) + (D[rm + cc + 1] - D[rm + cc - 1]);
-    T dy = T(4) * (D[rp + cc] - D[rm + cc]) + (D[rp + cc + 1] - D[rm + cc + 1]) + (D[rp + cc - 1] - D[rm + cc - 1]);
-    if (REFS) {
-        dx += T(4) * (B[r0 + cc + 1] - B[r0 + cc - 1]) + (B[rp + cc + 1] - B[rp + cc - 1]) + (B[rm + cc + 1] - B[rm + cc - 1]);
-        dy += T(4) * (B[rp + cc] - B[rm + cc]) + (B[rp + cc + 1] - B[rm + cc + 1]) + (B[rp + cc - 1] - B[rm + cc - 1]);
-    }
-    gx = dx * T(1.0 / 12.0);
-    gy = dy * T(1.0 / 12.0);
-}
-
-// REG = true: each node's populations stay in registers from B to D;
-// REG = false: B only reduces moments (rows spread evenly over the waves) and
-// D pulls each set again (from cache) right before its collision.
-template <typename R, typename S, int BY, bool REG>
-__device__ __forceinline__ void strip_body(const Ctx<R>& c, const StripRec& u, View src, View dst, Rsrc rsrc,
-                                           Rsrc rdst, StripSmem<R, BY, sizeof(R) == 4>& sh)
-{
-    static_assert(REG || BY == 4, "the moment-only row mapping is written for 4 rows per iteration");
-    constexpr bool REFS = sizeof(R) == 4;
-    using SM = StripSmem<R, BY, REFS>;
-    constexpr int M = SM::RING - 1, M1 = SM::RING1 - 1, W3 = SM::W3, W2 = SM::W2, W1 = SM::W1;
-    constexpr int NT = 64 * BY;
-    int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int x0 = u.x0, y0 = u.y0, y1 = u.y1;
-    const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
-
-    auto i3 = [&](int ux, int uy) { return (uy & M) * W3 + (ux - x0 + 3); };
-    auto i2 = [&](int ux, int uy) { return (uy & M) * W2 + (ux - x0 + 2); };
-    auto i1 = [&](int ux, int uy) { return (uy & M) * W1 + (ux - x0 + 1); };
-    auto ref_f = [&](int ux, int uy) -> R { return REFS ? sh.rf[i3(ux, uy)] : R(0); };
-    auto ref_q = [&](int ux, int uy) -> R { return REFS ? sh.rq[i3(ux, uy)] : R(0); };
-    auto ref_p = [&](int ux, int uy) -> R { return REFS ? sh.rp[i3(ux, uy)] : R(0); };
-    auto ref_t = [&](int ux, int uy) -> R { return REFS ? sh.rt[i3(ux, uy)] : R(0); };
-    // T - T_w(ux) of a node from its reference and the sum of its h deviations
-    auto t_dev = [&](int ux, R bt, R sum) -> R { return R((double)bt - c.Tlaw_d((double)ux)) + sum; };
-    // lattice node of an unwrapped coordinate (overhangs are shorter than the lattice)
-    auto wrapx = [&](int v) { return c.wallx ? v : (v < 0 ? v + c.nx : (v >= c.nx ? v - c.nx : v)); };
-    auto wrapy = [&](int v) { return c.wally ? v : (v < 0 ? v + c.ny : (v >= c.ny ? v - c.ny : v)); };
-    auto ghostx = [&](int v) { return c.wallx && (v < 0 || v >= c.nx); };
-    auto ghosty = [&](int v) { return c.wally && (v < 0 || v >= c.ny); };
-    // every pull of x0-3 .. x0+64 stays inside the lattice (no wrap, no wall)
-    const bool xint = x0 >= 3 && x0 + kStripW + 2 < c.nx;
-
-    // storage references of rows ra .. rb
-    auto load_refs = [&](int ra, int rb) {
-        if (!REFS) return;
-        const int n = (rb - ra + 1) * W3;
-        for (int k = tid; k < n; k += NT) {
-            const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
-            R a = R(0), b = R(0), d = R(0), t = R(0);
-            if (!ghostx(ux) && !ghosty(uy)) {
-                uint32_t lo, hi;
-                ref_ld(rsrc, (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)), lo, hi);
-                a = R(ref_get<0>(lo, hi));
-                b = R(ref_get<1>(lo, hi));
-                d = R(ref_get<2>(lo, hi));
-                t = R(ref_get<3>(lo, hi));
-            }
-            const int e = i3(ux, uy);
-            sh.rf[e] = a;
-            sh.rq[e] = b;
-            sh.rp[e] = d;
-            sh.rt[e] = t;
-        }
-    };
-
-    // the same for the next iteration's rows, split into issue and commit so
-    // that the loads are in flight during the normals (at most 2 slots per thread)
-    static_assert(BY * W3 <= 2 * NT, "reference prefetch holds two slots per thread");
-    auto ref_fetch = [&](int ra, int k, R& a, R& b, R& d, R& t) {
-        a = R(0);
-        b = R(0);
-        d = R(0);
-        t = R(0);
-        if (!REFS || k >= BY * W3) return;
-        const int ux = x0 - 3 + k % W3, uy = ra + k / W3;
-        if (!ghostx(ux) && !ghosty(uy)) {
-            uint32_t lo, hi;
-            ref_ld(rsrc, (uint32_t)(wrapy(uy) * c.pitch + wrapx(ux)), lo, hi);
-            a = R(ref_get<0>(lo, hi));
-            b = R(ref_get<1>(lo, hi));
-            d = R(ref_get<2>(lo, hi));
-            t = R(ref_get<3>(lo, hi));
-        }
-    };
-    auto ref_put = [&](int ra, int k, R a, R b, R d, R t) {
-        if (!REFS || k >= BY * W3) return;
-        const int e = i3(x0 - 3 + k % W3, ra + k / W3);
-        sh.rf[e] = a;
-        sh.rq[e] = b;
-        sh.rp[e] = d;
-        sh.rt[e] = t;
-    };
-
-    // p*, T, psi of the node at unwrapped (ux, uy) into the rings (ghosts: zeros)
-    auto moments_e1 = [&](auto intc, int ux, int uy) {
-        constexpr bool INT = decltype(intc)::value;
-        const bool gh = !INT && (ghostx(ux) || ghosty(uy));
-        const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
-        R v[9];
-        R pv = R(0), tv = R(0), qv = R(0);
-        const R bp = ref_p(ux, uy);
-        if (!gh) {
-            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, v);
-            pv = sum9(v);
-            const R bh = ref_t(ux, uy);
-            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, ref_t, v);
-            tv = t_dev(ux, bh, sum9(v));
-            const R bq = ref_q(ux, uy);
-            pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, v);
-            qv = bq + sum9(v);
-        }
-        const int e = i1(ux, uy);
-        sh.ps[e] = pv;
-        if (REFS) sh.psb[e] = gh ? R(0) : bp;
-        sh.ts[e] = tv;
-        sh.pq[e] = qv;
-    };
-
-    // phi and (e1) p*, T, psi of the node at unwrapped (ux, uy) into the rings;
-    // ghost nodes get zeros here and their mirror values in B2
-    auto moments = [&](auto intc, int ux, int uy, bool e1) {
-        constexpr bool INT = decltype(intc)::value;
-        const bool gh = !INT && (ghostx(ux) || ghosty(uy));
-        const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
-        R v[9];
-        const R bf = ref_f(ux, uy);
-        R d = R(0);
-        if (!gh) {
-            pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, v);
-            d = sum9(v);
-        }
-        const int e2 = i2(ux, uy);
-        sh.phd[e2] = d;
-        if (REFS) sh.phb[e2] = gh ? R(0) : bf;
-        if (e1) moments_e1(intc, ux, uy);
-    };
-
-    // populations of the wave's row, kept in registers until the collision
-    R F[9], G[9], H[9], Q[9];
-    auto own_pulls = [&](auto intc, int y) {
-        constexpr bool INT = decltype(intc)::value;
-        const int ux = x0 - 1 + lane, uy = y + wv;
-        const bool gh = !INT && (ghostx(ux) || ghosty(uy));
-        const int mx = INT ? ux : wrapx(ux), my = INT ? uy : wrapy(uy);
-        const R bf = ref_f(ux, uy), bq = ref_q(ux, uy), bp = ref_p(ux, uy);
-        const R bh = ref_t(ux, uy);
-        if (!gh) {
-            pull9<SET_F, INT, REFS, S>(c, src, ux, uy, mx, my, bf, ref_f, F);
-            pull9<SET_G, INT, REFS, S>(c, src, ux, uy, mx, my, bp, ref_p, G);
-            pull9<SET_H, INT, REFS, S>(c, src, ux, uy, mx, my, bh, ref_t, H);
-            pull9<SET_Q, INT, REFS, S>(c, src, ux, uy, mx, my, bq, ref_q, Q);
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) F[a] = G[a] = H[a] = Q[a] = R(0);
-        }
-        if (wv >= 2) {
-            const int e2 = i2(ux, uy);
-            sh.phd[e2] = gh ? R(0) : sum9(F);
-            if (REFS) sh.phb[e2] = gh ? R(0) : bf;
-        }
-        if (wv >= 1) {
-            const int e = i1(ux, uy);
-            sh.ps[e] = gh ? R(0) : sum9(G);
-            if (REFS) sh.psb[e] = gh ? R(0) : bp;
-            sh.ts[e] = gh ? R(0) : t_dev(ux, bh, sum9(H));
-            sh.pq[e] = gh ? R(0) : bq + sum9(Q);
-        }
-    };
-
-    // halo slots of iteration y: phi of rows y+BY+1 and y+BY (66 columns each;
-    // p*, T, psi too on the 64 E1 columns of row y+BY) and phi of the columns
-    // x0-2, x0+63 of rows y+2 .. y+BY-1; spread evenly over the waves
-    auto halo_pulls = [&](auto intc, int y) {
-        constexpr int NH = 2 * W2 + 2 * (BY - 2), CH = (NH + BY - 1) / BY;
-        const int k = wv * CH + lane;
-        if (lane >= CH || k >= NH) return;
-        int ux, uy;
-        bool e1 = false;
-        if (k < W2) {
-            uy = y + BY + 1;
-            ux = x0 - 2 + k;
-        } else if (k < 2 * W2) {
-            const int col = k - W2;
-            uy = y + BY;
-            ux = x0 - 2 + col;
-            e1 = col >= 1 && col <= W1;
-        } else {
-            const int m = k - 2 * W2;
-            uy = y + 2 + (m >> 1);
-            ux = (m & 1) ? x0 + kStripW + 1 : x0 - 2;
-        }
-        moments(intc, ux, uy, e1);
-    };
-
-    // B without registers: wave 0 row y+4 (phi, p*, T, psi), wave 1 row y+1
-    // (p*, T, psi) and row y+5 (phi), waves 2, 3 rows y+2, y+3 (phi, p*, T,
-    // psi), all on the 64 E1 columns; lanes 0 and 63 of wave j add phi of
-    // columns x0-2 and x0+63 on row y+2+j
-    auto moment_rows = [&](auto intc, int y) {
-        const int ux = x0 - 1 + lane;
-        if (wv == 0) {
-            moments(intc, ux, y + 4, true);
-        } else if (wv == 1) {
-            moments_e1(intc, ux, y + 1);
-            moments(intc, ux, y + 5, false);
-        } else {
-            moments(intc, ux, y + wv, true);
-        }
-        if (lane == 0) moments(intc, x0 - 2, y + 2 + wv, false);
-        if (lane == 63) moments(intc, x0 + kStripW + 1, y + 2 + wv, false);
-    };
-
-    // before the first iteration: phi of rows y0-2 .. y0+1, p*, T, psi of rows y0-1 .. y0
-    auto prologue = [&](auto intc) {
-        for (int k = tid; k < 4 * W2; k += NT) {
-            const int col = k % W2, uy = y0 - 2 + k / W2;
-            moments(intc, x0 - 2 + col, uy, uy >= y0 - 1 && col >= 1 && col <= W1);
-        }
-    };
-
-    // ghost nodes beyond walls: the mirror node's value (zero normal
-    // gradient) or 2 X_w - X(mirror) for Dirichlet T / psi; phi on rows
-    // pa .. pb, p*, T, psi on rows ea .. eb
-    auto ghost_fill = [&](int pa, int pb, int ea, int eb) {
-        const int ra = pa < ea ? pa : ea, rb = pb > eb ? pb : eb;
-        const int n = (rb - ra + 1) * W2;
-        for (int k = tid; k < n; k += NT) {
-            const int col = k % W2, uy = ra + k / W2, ux = x0 - 2 + col;
-            const bool gx = ghostx(ux), gy = ghosty(uy);
-            if (!gx && !gy) continue;
-            // ghosts more than two nodes beyond a wall are read by no live node
-            if ((gx && (ux < -2 || ux > c.nx + 1)) || (gy && (uy < -2 || uy > c.ny + 1))) continue;
-            int xs = -1, ys = -1, mx = wrapx(ux), my = wrapy(uy);
-            if (gx) { xs = ux < 0 ? 0 : 1; mx = ux < 0 ? -1 - ux : 2 * c.nx - 1 - ux; }
-            if (gy) { ys = uy < 0 ? 2 : 3; my = uy < 0 ? -1 - uy : 2 * c.ny - 1 - uy; }
-            const int mux = gx ? mx : ux, muy = gy ? my : uy;
-            if (uy >= pa && uy <= pb) {
-                const int e = i2(ux, uy), m = i2(mux, muy);
-                sh.phd[e] = sh.phd[m];
-                if (REFS) sh.phb[e] = sh.phb[m];
-            }
-            const int mc = mux - x0 + 1;
-            if (uy >= ea && uy <= eb && col >= 1 && col <= W1 && mc >= 0 && mc < W1) {
-                const int e = i1(ux, uy), m = i1(mux, muy);
-                sh.ps[e] = sh.ps[m];
-                if (REFS) sh.psb[e] = sh.psb[m];
-                double T = c.Tlaw_d((double)mux) + (double)sh.ts[m];
-                R q = sh.pq[m];
-                if (ys >= 0 && c.t_dir(ys)) T = 2.0 * c.Tlaw_d((double)mx) - T;
-                if (xs >= 0 && c.t_dir(xs)) T = 2.0 * c.Tlaw_d(xs ? c.nx - 0.5 : -0.5) - T;
-                if (ys >= 0 && c.p_dir(ys)) q = R(2) * c.psi_wall(ys) - q;
-                if (xs >= 0 && c.p_dir(xs)) q = R(2) * c.psi_wall(xs) - q;
-                sh.ts[e] = R(T - c.Tlaw_d((double)ux));
-                sh.pq[e] = q;
-            }
-        }
-    };
-
-    // unit normal and sigma(T, psi) of rows ra .. rb (one row per wave)
-    auto normals = [&](int ra, int rb) {
-        for (int uy = ra + wv; uy <= rb; uy += BY) {
-            const int ux = x0 - 1 + lane;
-            R gx, gy;
-            grad_ring<R, REFS>(sh.phd, sh.phb, ((uy - 1) & M) * W2, (uy & M) * W2, ((uy + 1) & M) * W2, lane + 1, gx, gy);
-            R mag = sqrt(gx * gx + gy * gy);
-            mag = mag < R(1e-12) ? R(1e-12) : mag;
-            const int e = (uy & M) * W1 + lane, en = (uy & M1) * W1 + lane;
-            sh.nx[en] = gx / mag;
-            sh.ny[en] = gy / mag;
-            sh.sg[en] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
-        }
-    };
-
-    // collision of the wave's row from the registers
-    auto collide_row = [&](auto intc, int y) {
-        constexpr bool INT = decltype(intc)::value;
-        const int x = x0 - 1 + lane, yy = y + wv;
-        if (lane < 1 || lane > kStripW || x >= c.nx || yy >= y1) return;
-        const int rm2 = ((yy - 1) & M) * W2, r02 = (yy & M) * W2, rp2 = ((yy + 1) & M) * W2;
-        const int rm1 = ((yy - 1) & M) * W1, r01 = (yy & M) * W1, rp1 = ((yy + 1) & M) * W1;
-        const int rmn = ((yy - 1) & M1) * W1, r0n = (yy & M1) * W1, rpn = ((yy + 1) & M1) * W1;
-        const int c2 = lane + 1, c1 = lane;
-        R gx, gy;
-        grad_ring<R, REFS>(sh.phd, sh.phb, rm2, r02, rp2, c2, gx, gy);
-        const R phb = REFS ? sh.phb[r02 + c2] : R(0);
-        const R phd = sh.phd[r02 + c2];
-        const R phi = phb + phd;
-        // 1 - phi from the reference / deviation pair (phi ~ 1 inside a bubble)
-        const R omphi = (R(1) - phb) - phd;
-        const R nxv = sh.nx[r0n + c1], nyv = sh.ny[r0n + c1];
-        // curvature: isotropic divergence of the normal field
-        const R* NX = sh.nx;
-        const R* NY = sh.ny;
-        const R kap = (R(4) * (NX[r0n + c1 + 1] - NX[r0n + c1 - 1] + NY[rpn + c1] - NY[rmn + c1]) +
-                       (NX[rpn + c1 + 1] - NX[rpn + c1 - 1] + NX[rmn + c1 + 1] - NX[rmn + c1 - 1]) +
-                       (NY[rpn + c1 + 1] - NY[rmn + c1 + 1] + NY[rpn + c1 - 1] - NY[rmn + c1 - 1])) *
-                      R(1.0 / 12.0);
-        double dsxd, dsyd;
-        grad_ring<R, false, double>(sh.sg, nullptr, rmn, r0n, rpn, c1, dsxd, dsyd);
-        const R dsx = R(dsxd), dsy = R(dsyd);
-        R dpx, dpy;
-        grad_ring<R, REFS, R>(sh.ps, sh.psb, rm1, r01, rp1, c1, dpx, dpy);
-        const R sig = R(sh.sg[r0n + c1]);
-        const R pbase = REFS ? sh.psb[r01 + c1] : R(0);
-        const R pstar = pbase + sh.ps[r01 + c1];
-
-        // CSF surface force: 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
-        const R ds = R(1.5) * c.W * (gx * gx + gy * gy);
-        const R nds = nxv * dsx + nyv * dsy;
-        const R Fsx = ds * (-sig * kap * nxv + dsx - nxv * nds);
-        const R Fsy = ds * (-sig * kap * nyv + dsy - nyv * nds);
-        // properties linear in phi
-        const R rho = c.rhoA + phi * c.drho;
-        const R mu = c.muA + phi * c.dmu;
-        const R omnu = R(1) / (mu / rho * inv_cs2 + R(0.5));
-        const R alpha = c.alphaA + phi * c.dalpha;
-        const R omT = R(1) / (alpha * inv_cs2 + R(0.5));
-        // pressure force -grad(p* - rho cs2), total force
-        const R Fpx = -dpx + cs2 * c.drho * gx;
-        const R Fpy = -dpy + cs2 * c.drho * gy;
-        const R Ftx = Fsx + c.Fx;
-        const R Fty = Fsy + c.Fy - (rho - c.rhoA) * c.grav;
-
-        const R bh = ref_t(x, yy);
-        const R bq = ref_q(x, yy);
-        // live nodes are lattice nodes: x, yy need no wrap
-        if (!REG) pull9<SET_G, INT, REFS, S>(c, src, x, yy, x, yy, pbase, ref_p, G);
-        // g: momentum, velocity and pressure
-        const R jx = G[1] - G[3] + G[5] - G[6] - G[7] + G[8];
-        const R jy = G[2] - G[4] + G[5] + G[6] - G[7] - G[8];
-        const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
-        const R uy = (jy + R(0.5) * cs2 * Fty) / (rho * cs2);
-        const R p = pstar + R(0.5) * (Fpx * ux + Fpy * uy);
-        const R dV = dV_lam(c, phi, omphi);
-
-        const uint32_t o = (uint32_t)(yy * c.pitch + x);
-        // the new p* reference is the FP16-rounded p* of this node
-        const R nbp = REFS ? R(__half2float(__float2half_rn((float)pstar))) : R(0);
-        if (REFS) {
-            const R pd = (pbase - nbp) + sh.ps[r01 + c1] + R(0.5) * (Fpx * ux + Fpy * uy);
-            collide_g_dev(G, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
-        } else {
-            collide_g(G, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
-        }
-        store9<SET_G, S>(c, dst, o, G);
-        // f: first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W;
-        // the new storage reference is the FP16-rounded phi of this node
-        if (!REG) pull9<SET_F, INT, REFS, S>(c, src, x, yy, x, yy, phb, ref_f, F);
-        const R mt = c.Mphi * R(4) * phi * omphi / c.W;
-        const R nbf = REFS ? R(__half2float(__float2half_rn((float)phi))) : R(0);
-        collide_ad(F, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
-        store9<SET_F, S>(c, dst, o, F);
-        // h: temperature
-        if (!REG) pull9<SET_H, INT, REFS, S>(c, src, x, yy, x, yy, bh, ref_t, H);
-        const R nbt = REFS ? R(__half2float(__float2half_rn((float)(bh + sum9(H))))) : R(0);
-        collide_ad(H, bh, nbt, R(0), R(0), omT, ux, uy);
-        store9<SET_H, S>(c, dst, o, H);
-        // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
-        if (!REG) pull9<SET_Q, INT, REFS, S>(c, src, x, yy, x, yy, bq, ref_q, Q);
-        const R psi = bq + sum9(Q);
-        const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
-        const R nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
-        collide_ad(Q, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
-        store9<SET_Q, S>(c, dst, o, Q);
-        if (REFS) {
-            ref_st(rdst, o, (float)nbf, (float)nbq, (float)nbp, (float)nbt);
-        }
-    };
-
-    const bool walls = c.wallx || c.wally;
-    // prologue: references of rows y0-3 .. y0+BY+2, fields of the rows below y0
-    load_refs(y0 - 3, y0 + BY + 2);
-    __syncthreads();
-    const bool intp = xint && y0 >= 3 && y0 + 2 < c.ny;
-    if (intp) prologue(BoolC<true>{});
-    else prologue(BoolC<false>{});
-    __syncthreads();
-    if (!intp && walls) {
-        ghost_fill(y0 - 2, y0 + 1, y0 - 1, y0);
-        __syncthreads();
-    }
-    normals(y0 - 1, y0);
-    for (int y = y0; y < y1; y += BY) {
-        // lane-derived indices are recomputed per iteration rather than kept
-        // live across the loop (hoisting them costs more registers than it saves)
-        asm volatile("" : "+v"(tid), "+v"(lane), "+v"(wv));
-        const bool it = xint && y >= 3 && y + BY + 2 < c.ny;
-        if (it) {
-            if (REG) {
-                own_pulls(BoolC<true>{}, y);
-                halo_pulls(BoolC<true>{}, y);
-            } else {
-                moment_rows(BoolC<true>{}, y);
-            }
-        } else {
-            if (REG) {
-                own_pulls(BoolC<false>{}, y);
-                halo_pulls(BoolC<false>{}, y);
-            } else {
-                moment_rows(BoolC<false>{}, y);
-            }
-        }
-        __syncthreads();
-        if (!it && walls) {
-            ghost_fill(y + 2, y + BY + 1, y + 1, y + BY);
-            __syncthreads();
-        }
-        const bool more = y + BY < y1;
-        R ra0, rb0, rd0, rt0, ra1, rb1, rd1, rt1;
-        if (more) {
-            ref_fetch(y + BY + 3, tid, ra0, rb0, rd0, rt0);
-            ref_fetch(y + BY + 3, tid + NT, ra1, rb1, rd1, rt1);
-        }
-        normals(y + 1, y + BY);
-        if (more) {
-            ref_put(y + BY + 3, tid, ra0, rb0, rd0, rt0);
-            ref_put(y + BY + 3, tid + NT, ra1, rb1, rd1, rt1);
-        }
-        __syncthreads();
-        if (REG || !it) collide_row(BoolC<false>{}, y);
-        else collide_row(BoolC<true>{}, y);
     }
 }
 

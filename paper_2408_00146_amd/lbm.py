@@ -129,9 +129,14 @@ def tile_shapes() -> list[tuple[int, int]]:
     return out
 
 
+KINDS = {0: "tile", 1: "walk", 2: "walkpf"}
+
+
 def tile_kinds() -> list[str]:
-    """'tile' or 'strip' for every step configuration index."""
-    return ["strip" if lib().lbm_tile_kind(i) == 1 else "tile" for i in range(lib().lbm_tile_count())]
+    """Kind of every step configuration index: 'tile' (one workgroup per
+    tile), 'walk' (resident workgroups walking the tile table) or 'walkpf'
+    (the walk with next-tile prefetch)."""
+    return [KINDS[lib().lbm_tile_kind(i)] for i in range(lib().lbm_tile_count())]
 
 
 def workspace_bytes(cases: list[dict]) -> int:

@@ -1,0 +1,135 @@
+#!/usr/bin/env python3
+"""Write the long-run oracle references under tests/golden/.
+
+Calls only the FP64 oracle (oracle/) and the parameter-only case module; no
+value here comes from the GPU library.  For each run it stores, in one
+compressed .npz:
+
+  diag_steps, diag       the oracle diagnostics (Sigma phi, Sigma psi,
+                         phi-weighted centroid and velocity, p_in, p_out,
+                         extrema) every `every` steps, step 0 included;
+  fields, stride         phi, p, ux, uy, T, psi at the last step on the nodes
+                         (y, x) with y % stride == x % stride == 0;
+  row, col               the same six fields at the last step along the row
+                         and the column through the initial bubble centre,
+                         at every node;
+  steps, oracle_sha256   the run length and the oracle source it came from.
+
+Runs (lattice units; the workloads of the parity tests):
+  fp32_runs   the four 1024x512 channels (NF and SRF at beta_s 0 and 0.2,
+              R = 80, W = 5), 20000 steps, diagnostics every 100 steps;
+  precision   the 2048x1024 channel (R = 128, W = 5, sigma_TT = 1e-4,
+              beta_s = 0.3), 10000 steps, diagnostics every 500 steps.
+
+The full set takes hours on an 8-core host.  Progress is checkpointed to
+--ckpt (populations every --ckpt-every steps), so an interrupted run resumes.
+
+    python tests/golden/make_long_runs.py --runs fp32_runs precision
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "oracle"))
+
+import oracle as O  # noqa: E402
+
+from paper_2408_00146_amd import cases  # noqa: E402
+
+FIELDS = ("phi", "p", "ux", "uy", "T", "psi")
+
+
+def oracle_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_oracle.c", "lbm_oracle.h"):
+        with open(os.path.join(ROOT, "oracle", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def runs() -> dict:
+    out = {}
+    for c in cases.config_fp32_runs():
+        out[f"fp32_runs_{c['label']}"] = (c, 20000, 100, 4)
+    out["precision_2048x1024"] = (cases.config_precision(cases.FP64), 10000, 500, 8)
+    return out
+
+
+def diag_vec(o) -> np.ndarray:
+    d = o.diag()
+    return np.array([d[k] for k in O.DIAG_NAMES], dtype=np.float64)
+
+
+def run_one(name: str, params: dict, steps: int, every: int, stride: int, ckpt_dir: str, ckpt_every: int):
+    dst = os.path.join(HERE, f"long_{name}.npz")
+    o = O.Oracle(params)
+    ck = os.path.join(ckpt_dir, f"{name}.npz")
+    diags, dsteps = [], []
+    start = 0
+    if os.path.exists(ck):
+        z = np.load(ck)
+        if str(z["oracle_sha256"]) == oracle_sha():
+            o.set_populations(z["pops"])
+            start = int(z["step"])
+            diags = list(z["diag"])
+            dsteps = list(z["diag_steps"])
+            print(f"{name}: resumed at step {start}", flush=True)
+    if start == 0:
+        diags, dsteps = [diag_vec(o)], [0]
+    t0 = time.time()
+    s = start
+    while s < steps:
+        k = min(every - s % every, steps - s)
+        o.step(k)
+        s += k
+        if s % every == 0 or s == steps:
+            diags.append(diag_vec(o))
+            dsteps.append(s)
+        if s % ckpt_every == 0 and s < steps:
+            np.savez(ck + ".tmp.npz", pops=o.populations(), step=s, diag=np.array(diags),
+                     diag_steps=np.array(dsteps), oracle_sha256=oracle_sha())
+            os.replace(ck + ".tmp.npz", ck)
+            rate = params["nx"] * params["ny"] * (s - start) / (time.time() - t0) / 1e6
+            print(f"{name}: step {s}/{steps}  {rate:.2f} MLUPS  xc {diags[-1][2]:.4f}", flush=True)
+    f = o.fields()
+    yc, xc = int(round(params["yc"])), int(round(params["xc"]))
+    np.savez_compressed(
+        dst,
+        diag_steps=np.array(dsteps, dtype=np.int64), diag=np.array(diags), diag_names=np.array(O.DIAG_NAMES),
+        fields=np.stack([f[k][::stride, ::stride] for k in FIELDS]), stride=stride,
+        field_names=np.array(FIELDS), row=np.stack([f[k][yc, :] for k in FIELDS]), row_y=yc,
+        col=np.stack([f[k][:, xc] for k in FIELDS]), col_x=xc, steps=steps, oracle_sha256=oracle_sha(),
+    )
+    print(f"{name}: wrote {dst} after {time.time() - t0:.0f} s", flush=True)
+    if os.path.exists(ck):
+        os.remove(ck)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--runs", nargs="*", default=["fp32_runs", "precision"])
+    ap.add_argument("--ckpt", default=os.path.join(ROOT, "_work", "golden_ckpt"))
+    ap.add_argument("--ckpt-every", type=int, default=2000)
+    args = ap.parse_args()
+    os.makedirs(args.ckpt, exist_ok=True)
+    O.build()
+    for name, (p, steps, every, stride) in runs().items():
+        if not any(name.startswith(r) for r in args.runs):
+            continue
+        if os.path.exists(os.path.join(HERE, f"long_{name}.npz")):
+            print(f"{name}: present, skipped", flush=True)
+            continue
+        run_one(name, p, steps, every, stride, args.ckpt, args.ckpt_every)
+
+
+if __name__ == "__main__":
+    main()

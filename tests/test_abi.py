@@ -70,10 +70,8 @@ def test_tile_table(L):
     shapes, kinds = lbm.tile_shapes(), lbm.tile_kinds()
     assert len(shapes) == len(kinds) == L.lbm_tile_count()
     tiles = [s for s, k in zip(shapes, kinds) if k == "tile"]
-    strips = [s for s, k in zip(shapes, kinds) if k == "strip"]
-    assert (64, 16) in tiles and (64, 4) in tiles and all(bx * by >= 256 for bx, by in tiles)
-    # strips: 62 columns, segments a multiple of the 4 rows marched per iteration
-    assert strips and all(bx == 62 and by % 4 == 0 for bx, by in strips)
+    assert (64, 8) in tiles and (64, 4) in tiles and all(bx * by >= 256 for bx, by in tiles)
+    assert set(kinds) <= {"tile", "walk", "walkpf"}
     assert kinds[0] == "tile"
     assert L.lbm_tile_shape(99, None, None) == lbm.LBM_E_INVAL
     assert L.lbm_tile_kind(99) == lbm.LBM_E_INVAL

@@ -102,7 +102,13 @@ typedef struct lbm_case {
     int64_t max_steps;       /* step budget of this case within a batched run; <= 0 = unlimited */
 } lbm_case;
 
-/* Diagnostics (FP64), reduced on the GPU in a fixed order. */
+/* Diagnostics (FP64), reduced on the GPU in a fixed order.  Sec. 6 follows a
+ * bubble by its position and by the average velocity inside it; both are
+ * taken phi-weighted here (x_c = sum x phi / sum phi, u_b = sum u phi /
+ * sum phi), and the Laplace test of Sec. 5.1 compares the pressure inside
+ * and outside the bubble (means over phi >= 0.99 and phi <= 0.01).
+ * Sum phi and sum psi are the totals that the phase-field and surfactant
+ * equations conserve (App. B, App. E). */
 typedef struct lbm_diag {
     double mass_phi, mass_psi;   /* sum of phi, sum of psi over the lattice */
     double xc, yc;               /* phi-weighted centroid */
@@ -131,24 +137,36 @@ typedef struct lbm_handle lbm_handle;
 /* Bytes of device workspace needed for these cases (256-byte aligned start). */
 size_t lbm_workspace_bytes(const lbm_case* cases, int32_t ncases);
 
-/* Validate the cases, lay out the workspace, build the tile and strip tables
- * and set the initial state of every case (tanh interface plus noise, linear
- * T, psi band, p from p_jump, u = 0; populations at rest equilibrium).  `workspace`
+/* Validate the cases, lay out the workspace, build the tile tables and set
+ * the initial state of every case: the equilibrium tanh profile of the
+ * phase field across the interface, phi = 1/2 + 1/2 tanh(2 d / W) with d
+ * the signed distance to the circle or band (Sec. 3), plus seeded noise;
+ * T on the linear wall law (Sec. 2); psi = psi_bulk + psi_gradx (x - xT0) +
+ * psi_band 4 phi (1 - phi); p = p_jump (3 phi^2 - 2 phi^3); u = 0; every set
+ * at its rest equilibrium (App. B-E at u = 0).  `workspace`
  * is device memory of at least lbm_workspace_bytes(), 256-byte aligned, owned
  * by the caller and used for everything the library keeps on the device (the
  * library allocates no device memory of its own; only the host-memory variants
  * of the field and population transfers below stage through a temporary
  * device buffer); `stream` is a hipStream_t (NULL =
  * default stream).  LBM_E_INVAL for: FP64 cases mixed with FP32/FP16S cases
- * in one handle; a case whose population buffer (36 values per node in its
+ * in one handle; an LBM_FP16S case with nx < 64 (narrower than one tile row); a case whose population buffer (36 values per node in its
  * storage type, pitch nx rounded up to 64) exceeds 4 GiB, the reach of the
  * 32-bit buffer offsets; more than 2^28 nodes in a case.  On success *out
  * receives the handle. */
 int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t bytes, void* stream,
              lbm_handle** out);
 
-/* Advance every case by nsteps time steps (each case stops at its max_steps).
- * Asynchronous on the handle's stream. */
+/* Advance every case by nsteps time steps (each case stops at its
+ * max_steps).  One step is the method's full update at every node: pull
+ * streaming with the wall rules (Sec. 2), the moments phi, p*, T, psi, j,
+ * the isotropic gradients and curvature (Sec. 3), sigma(T, psi) (Sec. 2.1),
+ * the CSF and pressure forces, u and p (Sec. 3, App. C), and the four
+ * central-moment collisions of App. B (f), C (g), D (h) and E (q) with the
+ * transformation matrices of App. F.  Asynchronous on the handle's stream:
+ * launches captured hipGraphs of up to 100 steps; returns LBM_E_DEVICE if a
+ * launch fails (the handle then holds the state of the last completed step
+ * on the device). */
 int lbm_step(lbm_handle* h, int64_t nsteps);
 
 /* Write the selected fields of one case at its current step into dst (FP64
@@ -168,26 +186,27 @@ int lbm_set_populations(lbm_handle* h, int32_t case_id, const void* src, int32_t
 int lbm_load_fields(lbm_handle* h, int32_t case_id, const void* phi, const void* T, const void* psi,
                     int32_t src_on_device);
 
-/* Reduce the diagnostics of one case (synchronizes the stream).  Returns
- * LBM_E_NONFINITE when any population is NaN/Inf; *out is filled either way. */
+/* Reduce the diagnostics of one case (the quantities of struct lbm_diag,
+ * Sec. 5.1 and Sec. 6) in FP64 on the GPU, in a fixed order, and copy them
+ * to *out (host memory owned by the caller).  Synchronizes the stream.
+ * Returns LBM_E_NONFINITE when any population is NaN/Inf; *out is filled
+ * either way. */
 int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
 
-/* Step-kernel configuration.  Index i < lbm_tile_count() selects either
- *   kind 0: one workgroup per bx x by tile (tile plus halo staged per step;
- *           with bx * by = 256 each thread owns one node and keeps its
- *           populations in registers from the moment pass to the collision), or
- *   kind 1: strip marching: one workgroup per strip of bx = 62 columns and
- *           segment of by rows, marching 4 rows per iteration with the
- *           reduced fields of the rows in flight kept in LDS ring buffers;
- *           cases with nx < 70 or ny < 16 are advanced by the tile kernel of
- *           configuration 0 in the same step.
- * Every configuration computes the same step (results agree to rounding of
- * identical operations).  lbm_autotune times every configuration valid for
- * this handle's cases (a trial step re-reads the current state and writes
- * only the scratch half of the ping-pong pair, so the state is unchanged)
- * and keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
+/* Step-kernel configuration.  Index i < lbm_tile_count() selects one
+ * workgroup per bx x by tile of the handle's tile table (kind 0), the tile
+ * plus its halo staged in LDS each step:
+ *   0: 64 x 8 tiles, two nodes per thread, each set pulled again right
+ *      before its collision;
+ *   1: 64 x 4 tiles, one node per thread, its 36 populations held in
+ *      registers from the moment pass to the collision (the default).
+ * Both compute the same step (results agree to rounding of identical
+ * operations).  lbm_autotune times every configuration valid for this
+ * handle's cases (a trial step re-reads the current state and writes only
+ * the scratch half of the ping-pong pair, so the state is unchanged) and
+ * keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
  * lbm_tile_shape / lbm_tile_kind describe an index (LBM_E_INVAL if out of
- * range).  A new handle starts with the 64 x 4 tiles (configuration 6). */
+ * range). */
 int lbm_autotune(lbm_handle* h, int32_t trial_steps);
 int lbm_tile_count(void);
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by);

@@ -31,18 +31,14 @@ constexpr int kOwnShape = 1;
 static_assert(kShapes[kOwnShape].bx * kShapes[kOwnShape].by == 256, "one node per thread");
 constexpr int kMacroBX = 64, kMacroBY = 8;
 
-// Step configurations.  kind 0 (tile): one workgroup per tile of the table.
-// kind 1 (walk): a grid of as many workgroups as the GPU holds at once, each
-// walking its share of the tile table; with `pf` a workgroup issues the
-// own-node loads of its next tile as soon as the current tile's are decoded,
-// so they are in flight while the current tile computes.
-enum { KIND_TILE = 0, KIND_WALK = 1 };
+// Step configurations: one workgroup per tile of the table, in either shape.
+// (A grid of resident workgroups walking the tile table, with or without
+// issuing the next tile's loads ahead, was measured slower on MI355X and is
+// not kept.)
 struct Config {
-    int kind, shape;
-    bool pf;
+    int shape;
 };
-constexpr Config kConfigs[] = {{KIND_TILE, 0, false}, {KIND_TILE, 1, false}, {KIND_WALK, 1, false},
-                               {KIND_WALK, 1, true}};
+constexpr Config kConfigs[] = {{0}, {1}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 constexpr int kDefaultConfig = 1;
 
@@ -69,28 +65,18 @@ __device__ __forceinline__ bool interior(const CaseDev& cd, int x0, int y0, int 
     return x0 >= 3 && y0 >= 3 && x0 + bx + 3 <= cd.nx && y0 + by + 3 <= cd.ny;
 }
 
-// Lattice geometry of a case (what the pull addressing needs).
-struct Geo {
-    int nx, ny, pitch, plane, wallx, wally;
-    __device__ explicit Geo(const CaseDev& c)
-        : nx(c.nx), ny(c.ny), pitch(c.pitch), plane((int)c.plane), wallx(c.wallx), wally(c.wally)
-    {
-    }
-};
-
-template <typename R, typename S, int BX, int BY, int MODE, bool PRE = false, typename NEXT = NoNext>
+template <typename R, typename S, int BX, int BY, int MODE>
 __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int x0, int y0, int b, Smem<R, BX, BY, sizeof(R) == 4>& sh,
-                                         const MacroOut& mo, double* dacc, Raw4<S>* pre = nullptr,
-                                         const NEXT& next = NEXT{})
+                                         const MacroOut& mo, double* dacc)
 {
     const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
     const View dst{make_rsrc(cd.buf[b ^ 1], MODE == MODE_STEP ? cd.pop_bytes : 0u)};
     const Rsrc rsrc = make_rsrc(cd.rbuf[b], cd.ref_bytes);
     const Rsrc rdst = make_rsrc(cd.rbuf[b ^ 1], MODE == MODE_STEP ? cd.ref_bytes : 0u);
     if (interior(cd, x0, y0, BX, BY))
-        tile_body<R, S, BX, BY, MODE, true, PRE>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc, pre, next);
+        tile_body<R, S, BX, BY, MODE, true>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
     else
-        tile_body<R, S, BX, BY, MODE, false, PRE>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc, pre, next);
+        tile_body<R, S, BX, BY, MODE, false>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
 }
 
 // Storage selection of a step launch: one storage type per kernel keeps the
@@ -104,13 +90,12 @@ using RealOf = typename std::conditional<ST == ST_F64, double, float>::type;
 template <int ST>
 using StoreOf = typename std::conditional<ST == ST_F64, double, typename std::conditional<ST == ST_F32, float, __half>::type>::type;
 
-// Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the 64 x 4
-// FP16-storage tiles, three (<= 168) for the FP32 64 x 4 tiles (they would
-// spill at 128), the FP64 64 x 4 tiles and every tile that carries prefetched
-// loads, two for FP64 64 x 8.
-constexpr int waves_of(int st, int bx, int by, bool pf)
+// Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the FP32 and
+// FP16-storage 64 x 4 tiles, three (<= 168) for the other FP32 tiles and the
+// FP64 64 x 4 tile, two for FP64 64 x 8.
+constexpr int waves_of(int st, int bx, int by)
 {
-    return st == ST_F64 ? (bx * by == 256 ? 3 : 2) : (bx * by == 256 && !pf ? 4 : 3);
+    return st == ST_F64 ? (bx * by == 256 ? 3 : 2) : (bx * by == 256 ? 4 : 3);
 }
 
 // The step's budget check: a case stops at its max_steps.
@@ -124,7 +109,7 @@ __device__ __forceinline__ bool tile_live(const CaseDev* cases, const TileRec& t
 
 // One workgroup per tile of the table.
 template <int ST, int BX, int BY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST, BX, BY, false)))) void k_step(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST, BX, BY)))) void k_step(
     const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles, int ntiles, const int64_t* __restrict__ steps,
     int t)
 {
@@ -140,73 +125,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST
     c.load(cd);
     const MacroOut mo{nullptr, 0u, nullptr};
     run_tile<R, S, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
-}
-
-// Issue the own-node loads of thread threadIdx.x in tile k (64 x 4).
-template <typename S>
-__device__ __forceinline__ void issue_own(const CaseDev* cases, const TileRec* tiles, const int64_t* steps, int t, int k,
-                                          Raw4<S> q[9])
-{
-    const TileRec tr = tiles[k];
-    int b;
-    (void)tile_live(cases, tr, steps, t, b);
-    const CaseDev& cd = cases[tr.c];
-    const Geo g(cd);
-    const View src{make_rsrc(cd.buf[b], cd.pop_bytes)};
-    int mx, my, tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    if (interior(cd, tr.x0, tr.y0, 64, 4)) {
-        (void)own_node<64>(g, tr.x0, tr.y0, tid, true, mx, my);
-        raw36<true, true, S>(g, src, mx, my, q);
-    } else if (own_node<64>(g, tr.x0, tr.y0, tid, false, mx, my)) {
-        raw36<false, true, S>(g, src, mx, my, q);
-    }
-}
-
-// A grid of resident workgroups walking the 64 x 4 tile table: workgroup b
-// takes tiles first, first + step, ... of its XCD's band (tiles of cases
-// whose step budget is spent are skipped).  PF: the next tile's own-node
-// loads are issued while the current tile computes.
-template <int ST, bool PF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST, 64, 4, PF)))) void k_walk(
-    const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles, int ntiles, const int64_t* __restrict__ steps,
-    int t)
-{
-    using R = RealOf<ST>;
-    using S = StoreOf<ST>;
-    constexpr int BX = 64, BY = 4;
-    __shared__ Smem<R, BX, BY, sizeof(R) == 4> sh;
-    const Band bd = xcd_band(blockIdx.x, gridDim.x, ntiles);
-    // first live tile at or after k on this workgroup's stride
-    auto next_live = [&](int k) {
-        int b;
-        while (k < bd.end && !tile_live(cases, tiles[k], steps, t, b)) k += bd.step;
-        return k;
-    };
-    int k = next_live(bd.first);
-    Raw4<S> pre[9];
-    if (PF && k < bd.end) issue_own<S>(cases, tiles, steps, t, k, pre);
-    const MacroOut mo{nullptr, 0u, nullptr};
-    while (k < bd.end) {
-        const int kn = next_live(k + bd.step);
-        const TileRec tr = tiles[k];
-        int b;
-        (void)tile_live(cases, tr, steps, t, b);
-        const CaseDev& cd = cases[tr.c];
-        Ctx<R> c;
-        c.load(cd);
-        if constexpr (PF) {
-            auto nxt = [&](Raw4<S>* q) {
-                if (kn < bd.end) issue_own<S>(cases, tiles, steps, t, kn, q);
-            };
-            run_tile<R, S, BX, BY, MODE_STEP, true>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr, pre, nxt);
-        } else {
-            run_tile<R, S, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
-        }
-        k = kn;
-        // the next tile's LDS writes must not overtake this tile's last reads
-        if (k < bd.end) __syncthreads();
-    }
 }
 
 // Deterministic block reduction of the diagnostic partials: wave64 butterfly
@@ -573,6 +491,11 @@ int validate(const lbm_case& c, int i)
     if (c.nx < 4 || c.ny < 4) return fail(LBM_E_INVAL, "case %d: nx, ny must be >= 4", i);
     if ((int64_t)c.nx * c.ny > (int64_t)1 << 28) return fail(LBM_E_INVAL, "case %d: lattice too large", i);
     if (c.precision < 0 || c.precision > 2) return fail(LBM_E_INVAL, "case %d: precision", i);
+    // FP16 storage on a lattice narrower than one tile row was followed by a GPU
+    // memory fault whose cause a CPU replay of every access of that handle did
+    // not find; such lattices are refused with FP16 storage (FP32 / FP64 run them)
+    if (c.precision == LBM_FP16S && c.nx < 64)
+        return fail(LBM_E_INVAL, "case %d: FP16 storage needs nx >= 64 (got %d); use FP32 for narrower lattices", i, c.nx);
     // one population buffer (36 planes) is addressed with 32-bit byte offsets
     if (case_pop_bytes(c) > (size_t)0xFFFFFF00u)
         return fail(LBM_E_INVAL, "case %d: %dx%d needs %zu bytes per population buffer; the limit is 4 GiB", i, c.nx,
@@ -674,10 +597,6 @@ using StepKernel = void (*)(const CaseDev*, const TileRec*, int, const int64_t*,
 template <int ST>
 StepKernel step_kernel_st(const Config& cf)
 {
-    if (cf.kind == KIND_WALK) {
-        if constexpr (ST == ST_F64) return k_walk<ST, false>;  // no prefetching FP64 walk (see config_ok)
-        else return cf.pf ? k_walk<ST, true> : k_walk<ST, false>;
-    }
     return cf.shape == 0 ? k_step<ST, 64, 8> : k_step<ST, 64, 4>;
 }
 
@@ -699,27 +618,10 @@ bool shape_ok(int shape, bool fp64)
     return lds <= 65536;
 }
 
-// Prefetching walks carry 36 extra registers per thread; FP64 tiles have no room for them.
 bool config_ok(int cfg, bool fp64)
 {
     if (cfg < 0 || cfg >= kNumConfigs) return false;
-    if (fp64 && kConfigs[cfg].pf) return false;
     return shape_ok(kConfigs[cfg].shape, fp64);
-}
-
-// Workgroups of a kernel resident on the whole GPU at once (its occupancy
-// times the compute units), cached per kernel.
-int resident_blocks(StepKernel k)
-{
-    static std::map<const void*, int> cache;
-    auto it = cache.find((const void*)k);
-    if (it != cache.end()) return it->second;
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k, 256, 0) != hipSuccess || cus <= 0 || per <= 0)
-        return 0;
-    cache[(const void*)k] = cus * per;
-    return cus * per;
 }
 
 }  // namespace
@@ -754,15 +656,8 @@ struct lbm_handle {
     int launch_part(const Config& cf, int st_part, int64_t t0, int64_t n, int t)
     {
         if (n <= 0) return LBM_OK;
-        const StepKernel k = step_kernel(st_part, cf);
-        int64_t grid = n;
-        if (cf.kind == KIND_WALK) {
-            const int res = resident_blocks(k);
-            if (res <= 0) return fail(LBM_E_DEVICE, "occupancy query of the walk kernel failed");
-            grid = std::min<int64_t>(n, res);
-        }
-        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), 0, stream, d_cases(), d_tiles(cf.shape) + t0, (int)n,
-                           d_steps(), t);
+        hipLaunchKernelGGL(step_kernel(st_part, cf), dim3((unsigned)n), dim3(256), 0, stream, d_cases(),
+                           d_tiles(cf.shape) + t0, (int)n, d_steps(), t);
         HIPCHK(hipGetLastError());
         return LBM_OK;
     }
@@ -1193,14 +1088,14 @@ int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by)
 int lbm_tile_kind(int32_t index)
 {
     if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    return kConfigs[index].kind == KIND_WALK ? (kConfigs[index].pf ? 2 : 1) : 0;
+    return 0;
 }
 
 int lbm_set_tile(lbm_handle* h, int32_t index)
 {
     CHECK_H(h);
     if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
-    if (!config_ok(index, h->fp64)) return fail(LBM_E_INVAL, "configuration %d is not available for FP64 cases", index);
+    if (!config_ok(index, h->fp64)) return fail(LBM_E_INVAL, "configuration %d exceeds the LDS budget for FP64", index);
     if (index != h->cfg) h->drop_graphs();
     h->cfg = index;
     return LBM_OK;

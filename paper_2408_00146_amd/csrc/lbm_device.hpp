@@ -904,28 +904,14 @@ __device__ __forceinline__ bool own_node(const CT& c, int x0, int y0, int tid, b
     return mx < c.nx && my < c.ny;
 }
 
-// No loads to issue for a following tile.
-struct NoNext {
-    template <typename Q>
-    __device__ __forceinline__ void operator()(Q*) const
-    {
-    }
-};
-
-// One step of one tile.  PRE: the own-node records of thread tid (one own
-// node per thread, 64 x 4 tiles) were loaded into `pre` before the call;
-// `next(pre)` is called as soon as they are decoded, so that loads for a
-// following tile can be issued into the same registers and stay in flight
-// while this tile computes.
-template <typename R, typename S, int BX, int BY, int MODE, bool INT, bool PRE = false, typename NEXT = NoNext>
+// One step of one tile.
+template <typename R, typename S, int BX, int BY, int MODE, bool INT>
 __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View src, View dst, Rsrc rsrc, Rsrc rdst,
-                                          Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc,
-                                          Raw4<S>* pre = nullptr, const NEXT& next = NEXT{})
+                                          Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc)
 {
     constexpr bool REFS = sizeof(R) == 4;
     constexpr int NT = 256;
     constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
-    static_assert(!PRE || OWN1, "preloaded own-node records need one own node per thread");
     // population loads of phase 1a issued before the storage references are
     // committed (one own node per thread; interior tiles, and with FP16
     // storage boundary tiles too).  FP64, and FP32 boundary tiles, keep the
@@ -933,8 +919,6 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     constexpr bool EARLY = OWN1 && (sizeof(S) == 2 || (INT && sizeof(S) == 4));
     constexpr int W3 = BX + 6, H3 = BY + 6, W2 = BX + 4, H2 = BY + 4, W1 = BX + 2, H1 = BY + 2;
     int tid = threadIdx.x;
-    // opaque from the start: inside a loop over tiles nothing derived from the
-    // thread index alone is hoisted out and kept live across tiles
     asm volatile("" : "+v"(tid));
     const R cs2 = R(1.0 / 3.0), inv_cs2 = R(3);
 
@@ -1080,9 +1064,8 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         };
         if constexpr (EARLY) {
             // loads, then the references, then the decoding
-            Raw4<S> qO_own[9], qA[9], qB[9];
-            Raw4<S>* qO = PRE ? pre : qO_own;
-            if (own_ok && !PRE) raw36<INT, true, S>(c, src, mx, my, qO);
+            Raw4<S> qO[9], qA[9], qB[9];
+            if (own_ok) raw36<INT, true, S>(c, src, mx, my, qO);
             if (a_ok && a_e1) raw36<INT, true, S>(c, src, amx, amy, qA);
             else if (a_ok) raw36<INT, false, S>(c, src, amx, amy, qA);
             if (b_ok) raw36<INT, false, S>(c, src, bmx, bmy, qB);
@@ -1118,7 +1101,6 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, bp, bh, bq, G, H, Q);
             }
-            if (PRE) next(pre);
         } else {
             // ring slots first, then the own node (fewer values live at once)
             {
@@ -1146,9 +1128,8 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R bf = ref_f(ux, uy), bp = ref_p(ux, uy), bq = ref_q(ux, uy);
             const R bh = ref_t(ux, uy);
             if (own_ok) {
-                Raw4<S> qO_own[9];
-                Raw4<S>* qO = PRE ? pre : qO_own;
-                if (!PRE) raw36<INT, true, S>(c, src, mx, my, qO);
+                Raw4<S> qO[9];
+                raw36<INT, true, S>(c, src, mx, my, qO);
                 fix9q<SET_F, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bf, ref_f, F);
                 fix9q<SET_G, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bp, ref_p, G);
                 fix9q<SET_H, INT, REFS, S, R>(c, qO, ux, uy, mx, my, bh, ref_t, H);
@@ -1156,7 +1137,6 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 put_f(olx, oly, bf, F);
                 put_ghq(olx, oly, ux, bp, bh, bq, G, H, Q);
             }
-            if (PRE) next(pre);
         }
     } else {
         // E1 slots (all four sets, their 36 loads issued together), then the

@@ -129,7 +129,7 @@ def tile_shapes() -> list[tuple[int, int]]:
     return out
 
 
-KINDS = {0: "tile", 1: "walk", 2: "walkpf"}
+KINDS = {0: "tile"}
 
 
 def tile_kinds() -> list[str]:

@@ -122,9 +122,11 @@ def main():
     args = ap.parse_args()
     os.makedirs(args.ckpt, exist_ok=True)
     O.build()
-    for name, (p, steps, every, stride) in runs().items():
-        if not any(name.startswith(r) for r in args.runs):
-            continue
+    todo = []
+    for r in args.runs:  # in the order given
+        todo += [n for n in runs() if n.startswith(r) and n not in todo]
+    for name in todo:
+        p, steps, every, stride = runs()[name]
         if os.path.exists(os.path.join(HERE, f"long_{name}.npz")):
             print(f"{name}: present, skipped", flush=True)
             continue

@@ -175,6 +175,18 @@ int lbm_step(lbm_handle* h, int64_t nsteps);
  * memory, the call stages through a temporary device buffer and synchronizes. */
 int lbm_moments(lbm_handle* h, int32_t case_id, uint32_t field_mask, void* dst, int32_t dst_on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fields as lbm_moments with a host destination, staged through a fixed
+ * device array of 64 MiB that the library holds on every device it runs on
+ * until the process ends, instead of a temporary device buffer.  dst_host is
+ * host memory of nf * nx * ny doubles (nf = set bits of field_mask, planes in
+ * mask-bit order), owned by the caller.  No device memory is allocated or
+ * freed.  LBM_E_INVAL when nf * nx * ny * 8 exceeds 64 MiB.  Synchronizes the
+ * stream.  All calls on one GPU share its array and every call rewrites the
+ * part it uses: calls that overlap in time on one device race. */
+int lbm_moments_static(lbm_handle* h, int32_t case_id, uint32_t field_mask, void* dst_host);
+
 /* Export / import the current populations of one case as FP64
  * [4][9][ny][nx] (checkpoint / restart).  Same dst/src conventions as
  * lbm_moments.  Import encodes into the case's storage precision. */

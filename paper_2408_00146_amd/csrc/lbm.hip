@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -624,6 +625,34 @@ bool config_ok(int cfg, bool fp64)
     return shape_ok(kConfigs[cfg].shape, fp64);
 }
 
+// Fixed device staging array of lbm_moments_static (callers that cannot
+// allocate): kStaticScratchBytes on every device the library runs on, held
+// until the process ends.  Host code never passes the symbol itself to a
+// kernel or copy: its device address is taken once per device with
+// hipGetSymbolAddress (with that device current) and kept here.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device ordinal -> device address of `scratch`
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_addr(void** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(LBM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return LBM_OK;
+}
+
 }  // namespace
 
 struct lbm_handle {
@@ -633,6 +662,7 @@ struct lbm_handle {
     std::vector<int64_t> steps;       // host mirror of the device step counters
     std::vector<int64_t> mtile_begin, mtile_count;
     hipStream_t stream = nullptr;
+    void* scratch = nullptr;  // this device's static staging array (lbm_moments_static)
     char* ws = nullptr;
     Layout L{};
     bool fp64 = false;
@@ -774,8 +804,14 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
     const Layout L = layout_of(cases, ncases);
     if (bytes < L.total) return fail(LBM_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, L.total);
 
+    void* scr = nullptr;
+    {
+        const int rc = scratch_addr(&scr);
+        if (rc != LBM_OK) return rc;
+    }
     lbm_handle* h = new (std::nothrow) lbm_handle();
     if (!h) return fail(LBM_E_NOMEM, "host allocation failed");
+    h->scratch = scr;
     h->ncases = ncases;
     h->cases.assign(cases, cases + ncases);
     h->stream = (hipStream_t)stream;
@@ -951,6 +987,27 @@ int lbm_moments(lbm_handle* h, int32_t case_id, uint32_t mask, void* dst, int32_
         if (rc == LBM_OK && e != hipSuccess) rc = fail(LBM_E_DEVICE, "lbm_moments copy: %s", hipGetErrorString(e));
     }
     return rc;
+}
+
+int lbm_moments_static(lbm_handle* h, int32_t case_id, uint32_t mask, void* dst_host)
+{
+    CHECK_H(h);
+    CHECK_CASE(h, case_id);
+    if (!dst_host) return fail(LBM_E_INVAL, "dst_host is null");
+    mask &= LBM_F_ALL;
+    if (!mask) return LBM_OK;
+    const lbm_case& c = h->cases[case_id];
+    const size_t nf = (size_t)__builtin_popcount(mask), bytes = nf * (size_t)c.nx * c.ny * sizeof(double);
+    if (bytes > kStaticScratchBytes)
+        return fail(LBM_E_INVAL, "lbm_moments_static: %zu field planes of %dx%d need %zu bytes; the static staging array holds %zu",
+                    nf, c.nx, c.ny, bytes, kStaticScratchBytes);
+    if (!h->scratch) return fail(LBM_E_STATE, "lbm_moments_static: no staging array on this handle's device");
+    // every live node writes every selected plane, so nothing needs clearing first
+    int rc = h->macro(case_id, mask, (double*)h->scratch, false);
+    if (rc != LBM_OK) return rc;
+    HIPCHK(hipMemcpyAsync(dst_host, h->scratch, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LBM_OK;
 }
 
 static int pops_io(lbm_handle* h, int case_id, double* out, const double* in, int on_device)

@@ -94,6 +94,7 @@ def lib():
         L.lbm_init.argtypes = [C.POINTER(LbmCase), i32, vp, sz, vp, C.POINTER(vp)]
         L.lbm_step.argtypes = [vp, i64]
         L.lbm_moments.argtypes = [vp, i32, u32, vp, i32]
+        L.lbm_moments_static.argtypes = [vp, i32, u32, vp]
         L.lbm_get_populations.argtypes = [vp, i32, vp, i32]
         L.lbm_set_populations.argtypes = [vp, i32, vp, i32]
         L.lbm_load_fields.argtypes = [vp, i32, vp, vp, vp, i32]
@@ -219,6 +220,19 @@ class Solver:
             _check(lib().lbm_moments(self._h, case, mask, C.c_void_p(out.data_ptr()), 1))
             if not device:
                 out = out.cpu().numpy()
+        return {k: out[i] for i, k in enumerate(ordered)}
+
+    def fields_static(self, case: int = 0, names=MACRO_FIELDS) -> dict:
+        """The fields of `fields`, fetched through lbm_moments_static (host
+        destination, staged through the library's fixed device array: no
+        device allocation)."""
+        mask = 0
+        for k in names:
+            mask |= 1 << FIELD_BITS[k]
+        ordered = sorted(names, key=lambda k: FIELD_BITS[k])
+        nx, ny = self.cases[case]["nx"], self.cases[case]["ny"]
+        out = np.empty((len(ordered), ny, nx), dtype=np.float64)
+        _check(lib().lbm_moments_static(self._h, case, mask, out.ctypes.data_as(C.c_void_p)))
         return {k: out[i] for i, k in enumerate(ordered)}
 
     def populations(self, case: int = 0) -> np.ndarray:

@@ -32,14 +32,16 @@ constexpr int kOwnShape = 1;
 static_assert(kShapes[kOwnShape].bx * kShapes[kOwnShape].by == 256, "one node per thread");
 constexpr int kMacroBX = 64, kMacroBY = 8;
 
-// Step configurations: one workgroup per tile of the table, in either shape.
-// (A grid of resident workgroups walking the tile table, with or without
-// issuing the next tile's loads ahead, was measured slower on MI355X and is
-// not kept.)
+// Step configurations: one workgroup of `nt` threads per tile of the table.
+// With nt = bx * by each thread owns one node and holds its populations in
+// registers from the moment pass to the collision; 64 x 8 tiles with 256
+// threads pull each set again before its collision.  (A grid of resident
+// workgroups walking the tile table, with or without issuing the next tile's
+// loads ahead, was measured slower on MI355X and is not kept.)
 struct Config {
-    int shape;
+    int shape, nt;
 };
-constexpr Config kConfigs[] = {{0}, {1}};
+constexpr Config kConfigs[] = {{0, 256}, {1, 256}, {0, 512}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 constexpr int kDefaultConfig = 1;
 
@@ -66,7 +68,7 @@ __device__ __forceinline__ bool interior(const CaseDev& cd, int x0, int y0, int 
     return x0 >= 3 && y0 >= 3 && x0 + bx + 3 <= cd.nx && y0 + by + 3 <= cd.ny;
 }
 
-template <typename R, typename S, int BX, int BY, int MODE>
+template <typename R, typename S, int BX, int BY, int MODE, int NT = 256>
 __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int x0, int y0, int b, Smem<R, BX, BY, sizeof(R) == 4>& sh,
                                          const MacroOut& mo, double* dacc)
 {
@@ -75,9 +77,9 @@ __device__ __forceinline__ void run_tile(const CaseDev& cd, const Ctx<R>& c, int
     const Rsrc rsrc = make_rsrc(cd.rbuf[b], cd.ref_bytes);
     const Rsrc rdst = make_rsrc(cd.rbuf[b ^ 1], MODE == MODE_STEP ? cd.ref_bytes : 0u);
     if (interior(cd, x0, y0, BX, BY))
-        tile_body<R, S, BX, BY, MODE, true>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
+        tile_body<R, S, BX, BY, MODE, true, NT>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
     else
-        tile_body<R, S, BX, BY, MODE, false>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
+        tile_body<R, S, BX, BY, MODE, false, NT>(c, x0, y0, src, dst, rsrc, rdst, sh, mo, dacc);
 }
 
 // Storage selection of a step launch: one storage type per kernel keeps the
@@ -92,11 +94,12 @@ template <int ST>
 using StoreOf = typename std::conditional<ST == ST_F64, double, typename std::conditional<ST == ST_F32, float, __half>::type>::type;
 
 // Waves per SIMD asked of the compiler: four (<= 128 VGPRs) for the FP32 and
-// FP16-storage 64 x 4 tiles, three (<= 168) for the other FP32 tiles and the
-// FP64 64 x 4 tile, two for FP64 64 x 8.
-constexpr int waves_of(int st, int bx, int by)
+// FP16-storage tiles with one node per thread, three (<= 168) for the other
+// FP32 tiles and the FP64 64 x 4 tile, two for the other FP64 tiles.
+constexpr int waves_of(int st, int bx, int by, int nt)
 {
-    return st == ST_F64 ? (bx * by == 256 ? 3 : 2) : (bx * by == 256 ? 4 : 3);
+    const bool own1 = bx * by == nt;
+    return st == ST_F64 ? (own1 && nt == 256 ? 3 : 2) : (own1 ? 4 : 3);
 }
 
 // The step's budget check: a case stops at its max_steps.
@@ -109,8 +112,8 @@ __device__ __forceinline__ bool tile_live(const CaseDev* cases, const TileRec& t
 }
 
 // One workgroup per tile of the table.
-template <int ST, int BX, int BY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST, BX, BY)))) void k_step(
+template <int ST, int BX, int BY, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_of(ST, BX, BY, NT)))) void k_step(
     const CaseDev* __restrict__ cases, const TileRec* __restrict__ tiles, int ntiles, const int64_t* __restrict__ steps,
     int t)
 {
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_of(ST
     Ctx<R> c;
     c.load(cd);
     const MacroOut mo{nullptr, 0u, nullptr};
-    run_tile<R, S, BX, BY, MODE_STEP>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
+    run_tile<R, S, BX, BY, MODE_STEP, NT>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
 }
 
 // Deterministic block reduction of the diagnostic partials: wave64 butterfly
@@ -562,7 +565,7 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
     d.Fx = c.Fext_x;
     d.Fy = c.Fext_y;
     d.grav = c.gravity;
-    d.scale = c.precision == LBM_FP16S ? 1024.0 : 1.0;
+    d.scale = c.precision == LBM_FP16S ? (double)kFp16Scale : 1.0;
     d.inv_scale = 1.0 / d.scale;
     d.plane = plane_of(c);
     d.max_steps = c.max_steps;
@@ -598,7 +601,8 @@ using StepKernel = void (*)(const CaseDev*, const TileRec*, int, const int64_t*,
 template <int ST>
 StepKernel step_kernel_st(const Config& cf)
 {
-    return cf.shape == 0 ? k_step<ST, 64, 8> : k_step<ST, 64, 4>;
+    if (cf.nt == 512) return k_step<ST, 64, 8, 512>;
+    return cf.shape == 0 ? k_step<ST, 64, 8, 256> : k_step<ST, 64, 4, 256>;
 }
 
 StepKernel step_kernel(int st, const Config& cf)
@@ -686,7 +690,7 @@ struct lbm_handle {
     int launch_part(const Config& cf, int st_part, int64_t t0, int64_t n, int t)
     {
         if (n <= 0) return LBM_OK;
-        hipLaunchKernelGGL(step_kernel(st_part, cf), dim3((unsigned)n), dim3(256), 0, stream, d_cases(),
+        hipLaunchKernelGGL(step_kernel(st_part, cf), dim3((unsigned)n), dim3(cf.nt), 0, stream, d_cases(),
                            d_tiles(cf.shape) + t0, (int)n, d_steps(), t);
         HIPCHK(hipGetLastError());
         return LBM_OK;

@@ -44,6 +44,8 @@ __host__ __device__ constexpr double wt(int a) { return a == 0 ? 4.0 / 9.0 : (a 
 
 enum { SET_F = 0, SET_G = 1, SET_H = 2, SET_Q = 3 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16S = 2 };
+// FP16 storage keeps deviations times 2^10.
+constexpr int kFp16Scale = 1024;
 
 // ------------------------------------------------------- case parameters
 // Device copy of one case, precomputed on the host.
@@ -585,8 +587,8 @@ __device__ __forceinline__ void store9x2(const Ctx<R>& c, View dst, uint32_t o, 
         Vec<S>::st2e(dst.r, o * (4u * E), (uint32_t)(d * c.plane * 4 + K) * E, a[d], b[d], c.scale);
 }
 
-// FP16 storage: whole four-set records of node o, from f and g (compute
-// type) and the already packed (h, q) words.
+// FP16 storage: whole four-set records of node o, from f and g (already
+// scaled by 2^10) and the already packed (h, q) words.
 template <typename R>
 __device__ __forceinline__ void store9x4h(const Ctx<R>& c, View dst, uint32_t o, const R f[9], const R g[9],
                                           const uint32_t hq[9])
@@ -596,7 +598,7 @@ __device__ __forceinline__ void store9x4h(const Ctx<R>& c, View dst, uint32_t o,
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
             decltype(__builtin_amdgcn_raw_buffer_load_b64(dst.r, 0, 0, 0)) w;
-            w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f[d] * c.scale, g[d] * c.scale));
+            w[0] = __builtin_bit_cast(uint32_t, __floats2half2_rn(f[d], g[d]));
             w[1] = hq[d];
             __builtin_amdgcn_raw_buffer_store_b64(w, dst.r, o * 8u, (uint32_t)(d * c.plane) * 8u, decltype(pol)::value);
         }
@@ -665,20 +667,27 @@ __device__ __forceinline__ R dV_lam(const Ctx<R>& c, R phi, R omphi)
 
 // ----------------------------------------------------------- collisions
 // Inverse raw-moment map P^-1 (App. F) from raw moments
-// m = (00, 10, 01, 20, 02, 11, 21, 12, 22).
-template <typename R>
+// m = (00, 10, 01, 20, 02, 11, 21, 12, 22), times OS (the output scale of
+// the FP16 store, 2^10, or 1): rows that share a pair of moments take it from
+// one partial sum (o1/o3, o2/o4, o5/o7, o6/o8), and OS rides on the 1/2 and
+// 1/4 of the rows (a power of two, so the scaled results are exactly OS times
+// the unscaled ones).
+template <int OS, typename R>
 __device__ __forceinline__ void raw_to_pop(const R m[9], R o[9])
 {
-    const R h = R(0.5), q = R(0.25);
-    o[0] = m[0] - m[3] - m[4] + m[8];
-    o[1] = h * (m[1] + m[3] - m[7] - m[8]);
-    o[2] = h * (m[2] + m[4] - m[6] - m[8]);
-    o[3] = h * (-m[1] + m[3] + m[7] - m[8]);
-    o[4] = h * (-m[2] + m[4] + m[6] - m[8]);
-    o[5] = q * (m[5] + m[6] + m[7] + m[8]);
-    o[6] = q * (-m[5] + m[6] - m[7] + m[8]);
-    o[7] = q * (m[5] - m[6] - m[7] + m[8]);
-    o[8] = q * (-m[5] - m[6] + m[7] + m[8]);
+    const R h = R(0.5 * OS), q = R(0.25 * OS);
+    const R a = m[3] - m[8], b = m[1] - m[7], c = m[4] - m[8], d = m[2] - m[6];
+    const R e = m[8] + m[5], f = m[6] + m[7], g = m[8] - m[5], k = m[6] - m[7];
+    o[0] = (m[0] - m[4]) - a;
+    if (OS != 1) o[0] *= R(OS);
+    o[1] = h * (a + b);
+    o[3] = h * (a - b);
+    o[2] = h * (c + d);
+    o[4] = h * (c - d);
+    o[5] = q * (e + f);
+    o[7] = q * (e - f);
+    o[6] = q * (g + k);
+    o[8] = q * (g - k);
 }
 
 // Advection-diffusion central-moment collision (f: App. B, h: App. D,
@@ -691,14 +700,16 @@ __device__ __forceinline__ void raw_to_pop(const R m[9], R o[9])
 // dM(u) = F^-1(u)(1,0,0,1/3,1/3,0,0,0,1/9) minus its u = 0 value and
 // A(u, a) = F^-1(u)(0, a_x, a_y, 0, ...).  With Xin = Xout = 0 this is the
 // plain P^-1 F^-1(u) of the post-collision central moments.
-template <typename R>
+// OS: output scale (the values returned are OS times the deviations).
+template <int OS = 1, typename R>
 __device__ __forceinline__ void collide_ad(R d[9], R Xin, R Xout, R jx, R jy, R w1, R ux, R uy)
 {
     const R Xd = sum9(d);
     const R X = Xin + Xd;
     const R Xshift = (Xin - Xout) + Xd;  // X - Xout without forming X first
-    const R mx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
-    const R my = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+    const R p57 = d[5] - d[7], p86 = d[8] - d[6];
+    const R mx = (d[1] - d[3]) + p57 + p86;
+    const R my = (d[2] - d[4]) + p57 - p86;
     const R kx = mx - ux * X, ky = my - uy * X;
     const R ax = kx + w1 * (jx - kx), ay = ky + w1 * (jy - ky);
     const R third = R(1.0 / 3.0);
@@ -714,15 +725,15 @@ __device__ __forceinline__ void collide_ad(R d[9], R Xin, R Xout, R jx, R jy, R 
     v[7] = X * (ux * uyy + third * ux) + uyy * ax + R(2) * uxy * ay;
     v[8] = X * (uxx * uyy + third * (uxx + uyy)) + R(2) * uxy * uy * ax + R(2) * uxy * ux * ay;
     R o[9];
-    raw_to_pop(v, o);
+    raw_to_pop<OS>(v, o);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) d[a] = R(wt(a)) * Xshift + o[a];
+    for (int a = 0; a < 9; ++a) d[a] = R(wt(a) * OS) * Xshift + o[a];
 }
 
 // Two-fluid central-moment collision (App. C): every moment relaxes with
 // rate 1 except the deviatoric second moments (2d, 11) at omega_nu, and each
 // takes (1 - w/2) times its source moment.
-template <typename R>
+template <int OS = 1, typename R>
 __device__ __forceinline__ void collide_g(R g[9], R pstar, R jx, R jy, R p, R rho, R ux, R uy, R Ftx, R Fty,
                                           R Fpx, R Fpy, R om)
 {
@@ -770,7 +781,7 @@ __device__ __forceinline__ void collide_g(R g[9], R pstar, R jx, R jy, R p, R rh
     m[7] = ux * uyy * t00 + uyy * t10 + R(2) * uxy * t01 + ux * t02 + R(2) * uy * t11 + q12;
     m[8] = uxx * uyy * t00 + R(2) * ux * uyy * t10 + R(2) * uxx * uy * t01 + uyy * t20 + uxx * t02 +
            R(4) * uxy * t11 + R(2) * uy * q21 + R(2) * ux * q12 + q22;
-    raw_to_pop(m, g);
+    raw_to_pop<OS>(m, g);
 }
 
 // The same collision with g held as deviations from w_a b (b = the node's
@@ -779,7 +790,7 @@ __device__ __forceinline__ void collide_g(R g[9], R pstar, R jx, R jy, R p, R rh
 // 1/3, 1/3, 0, 0, 0, 1/9); subtracting nb times them before P^-1 leaves every
 // large term out of the stored values.  pd = p - nb is formed by the caller
 // from (b - nb) + sum(dev) + F_p.u / 2 without cancellation.
-template <typename R>
+template <int OS = 1, typename R>
 __device__ __forceinline__ void collide_g_dev(R g[9], R pstar, R jx, R jy, R pd, R nb, R rho, R ux, R uy, R Ftx,
                                               R Fty, R Fpx, R Fpy, R om)
 {
@@ -825,7 +836,7 @@ __device__ __forceinline__ void collide_g_dev(R g[9], R pstar, R jx, R jy, R pd,
     m[7] = ux * uyy * T00 + uyy * t10 + R(2) * uxy * t01 + ux * T02 + R(2) * uy * t11 + q12;
     m[8] = uxx * uyy * T00 + R(2) * ux * uyy * t10 + R(2) * uxx * uy * t01 + uyy * T20 + uxx * T02 +
            R(4) * uxy * t11 + R(2) * uy * q21 + R(2) * ux * q12 + q22p;
-    raw_to_pop(m, g);
+    raw_to_pop<OS>(m, g);
 }
 
 // ------------------------------------------------------------ tile body
@@ -905,12 +916,12 @@ __device__ __forceinline__ bool own_node(const CT& c, int x0, int y0, int tid, b
 }
 
 // One step of one tile.
-template <typename R, typename S, int BX, int BY, int MODE, bool INT>
+// NT threads per workgroup; with NT = BX * BY each thread owns one node.
+template <typename R, typename S, int BX, int BY, int MODE, bool INT, int NT = 256>
 __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View src, View dst, Rsrc rsrc, Rsrc rdst,
                                           Smem<R, BX, BY, sizeof(R) == 4>& sh, const MacroOut& mo, double* dacc)
 {
     constexpr bool REFS = sizeof(R) == 4;
-    constexpr int NT = 256;
     constexpr bool OWN1 = BX * BY == NT && MODE == MODE_STEP;
     // population loads of phase 1a issued before the storage references are
     // committed (one own node per thread; interior tiles, and with FP16
@@ -1010,6 +1021,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         // (outer ring: 9); the sums and LDS writes follow.
         constexpr int NR1 = 2 * W1 + 2 * BY, NR2 = 2 * W2 + 2 * (BY + 2), NR = NR1 + NR2;
         static_assert(NR1 <= NT && NR <= 2 * NT && NR - NT <= NR2, "ring slots per thread");
+        constexpr bool TWO = NR > NT;  // some threads pull a second ring slot
         // E2 coordinates of ring slot r: the E1 ring first, then the outer E2 ring
         auto ring_slot = [&](int r, int& lx, int& ly) {
             if (r < 2 * W1) {
@@ -1042,9 +1054,13 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         const int olx = tid % BX + 2, oly = tid / BX + 2;
         const int ux = x0 + tid % BX, uy = y0 + tid / BX;
         const bool own_ok = own_node<BX>(c, x0, y0, tid, INT, mx, my);
-        ring_slot(tid, alx, aly);
-        const bool a_ok = node_of(alx, aly, aux, auy, amx, amy), a_e1 = tid < NR1;
-        const bool b_has = tid + NT < NR;
+        // ring slot a = tid (threads past the last ring slot take the last one's
+        // coordinates, so that the unconditional reference reads stay in the window)
+        const bool a_has = tid < NR;
+        ring_slot(a_has ? tid : NR - 1, alx, aly);
+        const bool a_in = node_of(alx, aly, aux, auy, amx, amy);
+        const bool a_ok = a_has && a_in, a_e1 = tid < NR1;
+        const bool b_has = TWO && tid + NT < NR;
         ring_slot(b_has ? tid + NT : NR - 1, blx, bly);
         // coordinates set on every thread (the reference read below is unconditional)
         const bool b_in = node_of(blx, bly, bux, buy, bmx, bmy);
@@ -1210,8 +1226,9 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         grad2<R, REFS>(sh.phd, sh.phb, ly * W2 + lx, W2, gx, gy);
         R mag = sqrt(gx * gx + gy * gy);
         mag = mag < R(1e-12) ? R(1e-12) : mag;
-        sh.nx[e] = gx / mag;
-        sh.ny[e] = gy / mag;
+        const R imag = R(1) / mag;
+        sh.nx[e] = gx * imag;
+        sh.ny[e] = gy * imag;
         const int ux = x0 - 1 + e % W1;
         sh.sg[e] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
     }
@@ -1258,7 +1275,8 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         // properties linear in phi
         const R rho = c.rhoA + phi * c.drho;
         const R mu = c.muA + phi * c.dmu;
-        const R omnu = R(1) / (mu / rho * inv_cs2 + R(0.5));
+        // omega_nu = 1 / (nu / cs2 + 1/2) with nu = mu / rho, as one division
+        const R omnu = rho / (mu * inv_cs2 + R(0.5) * rho);
         const R alpha = c.alphaA + phi * c.dalpha;
         const R omT = R(1) / (alpha * inv_cs2 + R(0.5));
         // pressure force -grad(p* - rho cs2), total force
@@ -1277,8 +1295,12 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         } else {
             pull9<SET_G, INT, REFS, S>(c, src, x, y, x, y, pbase, ref_p, g);
         }
-        const R jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
-        const R jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
+        const R g57 = g[5] - g[7], g86 = g[8] - g[6];
+        const R jx = (g[1] - g[3]) + g57 + g86;
+        const R jy = (g[2] - g[4]) + g57 - g86;
+        // u = (j + cs2 F_t / 2) / (rho cs2), each component correctly rounded
+        // (one reciprocal for both, multiplied in, raised the FP32 velocity
+        // error against the oracle threefold on the 128 x 64 channel)
         const R ux = (jx + R(0.5) * cs2 * Ftx) / (rho * cs2);
         const R uy = (jy + R(0.5) * cs2 * Fty) / (rho * cs2);
         const R p = pstar + R(0.5) * (Fpx * ux + Fpy * uy);
@@ -1330,24 +1352,27 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         // the new storage references are the FP16-rounded phi, psi, p* of this node
         const R nbp = REFS ? R(__half2float(__float2half_rn((float)pstar))) : R(0);
         const R nbf = REFS ? R(__half2float(__float2half_rn((float)phi))) : R(0);
+        // The collisions return OS times the new deviations: OS = 2^10 where
+        // FP16 records are encoded straight from them, 1 elsewhere.
+        constexpr int OS = (OWN1 && sizeof(S) == 2) ? kFp16Scale : 1;
         auto do_g = [&](R* gg) {
             if (REFS) {
                 const R pd = (pbase - nbp) + sh.ps[p1] + R(0.5) * (Fpx * ux + Fpy * uy);
-                collide_g_dev(gg, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+                collide_g_dev<OS>(gg, pstar, jx, jy, pd, nbp, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
             } else {
-                collide_g(gg, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
+                collide_g<OS>(gg, pstar, jx, jy, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omnu);
             }
         };
         // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W
         auto do_f = [&](R* f) {
             const R mt = c.Mphi * R(4) * phi * omphi / c.W;
-            collide_ad(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
+            collide_ad<OS>(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
         };
         // h: temperature; the new storage reference is the FP16-rounded T of this node
         R nbt = R(0);
         auto do_h = [&](R* hh) {
             nbt = REFS ? R(__half2float(__float2half_rn((float)(bh + sum9(hh))))) : R(0);
-            collide_ad(hh, bh, nbt, R(0), R(0), omT, ux, uy);
+            collide_ad<OS>(hh, bh, nbt, R(0), R(0), omT, ux, uy);
         };
         // q: surfactant, first-order equilibrium -D_psi psi (1 - psi) R/lambda
         R nbq = R(0);
@@ -1355,7 +1380,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
             const R psi = bq + sum9(qq);
             const R mf = -c.Dpsi * psi * (R(1) - psi) * dV;
             nbq = REFS ? R(__half2float(__float2half_rn((float)psi))) : R(0);
-            collide_ad(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
+            collide_ad<OS>(qq, bq, nbq, mf * gx, mf * gy, c.om_psi, ux, uy);
         };
         if constexpr (OWN1) {
             // held sets in pairs of adjacent sets (h, q), then (f, g), each
@@ -1368,8 +1393,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 // then whole 8-byte records stored (full cache lines per wave)
                 uint32_t hq[9];
 #pragma unroll
-                for (int d = 0; d < 9; ++d)
-                    hq[d] = __builtin_bit_cast(uint32_t, __floats2half2_rn(H[d] * c.scale, Q[d] * c.scale));
+                for (int d = 0; d < 9; ++d) hq[d] = __builtin_bit_cast(uint32_t, __floats2half2_rn(H[d], Q[d]));
                 do_f(F);
                 do_g(g);
                 store9x4h(c, dst, o, F, g, hq);

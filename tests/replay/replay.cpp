@@ -64,7 +64,7 @@ int main(int argc, char** argv)
     std::vector<lbm_case> cs(n);
     memcpy(cs.data(), raw.data(), n * sizeof(lbm_case));
     const int nsteps = atoi(argv[2]), cfg = atoi(argv[3]);
-    const int bx = kShapes[kConfigs[cfg].shape].bx, by = kShapes[kConfigs[cfg].shape].by;
+    const int bx = kShapes[kConfigs[cfg].shape].bx, by = kShapes[kConfigs[cfg].shape].by, nthr = kConfigs[cfg].nt;
     bool any64 = false;
     for (int i = 0; i < n; ++i) {
         if (validate(cs[i], i) != LBM_OK) { fprintf(stderr, "invalid: %s\n", g_err); return 2; }
@@ -105,11 +105,16 @@ int main(int argc, char** argv)
         for (int t = 0; t < k; ++t) {
             auto run = [&](const char* nm, int st, int64_t t0, int64_t cnt) {
                 if (cnt <= 0) return;
-                launch(nm, (unsigned)cnt, 1, 256, [&] {
-                    if (st == ST_F64) (bx == 64 && by == 4 ? k_step<ST_F64, 64, 4> : k_step<ST_F64, 64, 8>)(dev.data(), tiles.data() + t0, (int)cnt, steps.data(), t);
-                    else if (st == ST_F16) (bx == 64 && by == 4 ? k_step<ST_F16, 64, 4> : k_step<ST_F16, 64, 8>)(dev.data(), tiles.data() + t0, (int)cnt, steps.data(), t);
-                    else (bx == 64 && by == 4 ? k_step<ST_F32, 64, 4> : k_step<ST_F32, 64, 8>)(dev.data(), tiles.data() + t0, (int)cnt, steps.data(), t);
-                });
+                using K = void (*)(const CaseDev*, const TileRec*, int, const int64_t*, int);
+                auto pick = [&](auto stc) -> K {
+                    constexpr int ST = decltype(stc)::value;
+                    if (nthr == 512) return k_step<ST, 64, 8, 512>;
+                    return by == 4 ? k_step<ST, 64, 4, 256> : k_step<ST, 64, 8, 256>;
+                };
+                const K k = st == ST_F64 ? pick(std::integral_constant<int, ST_F64>{})
+                          : st == ST_F16 ? pick(std::integral_constant<int, ST_F16>{})
+                                         : pick(std::integral_constant<int, ST_F32>{});
+                launch(nm, (unsigned)cnt, 1, (unsigned)nthr, [&] { k(dev.data(), tiles.data() + t0, (int)cnt, steps.data(), t); });
             };
             if (any64) run("k_step<F64>", ST_F64, 0, nt);
             else {

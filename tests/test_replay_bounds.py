@@ -73,7 +73,7 @@ def test_fp16_flat_interface_handle(replay):
         assert np.all(np.isfinite(o["psi"])) and abs(float(o["psi"].min()) - pb) < 1e-2
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
 def test_mixed_storage_batch(replay, cfg):
     ps = [cases.channel(100, 52, 9.0, 4.0, sigma_TT=1e-3, beta_s=0.2, precision=cases.FP16S),
           cases.channel(70, 36, 6.0, 4.0, sigma_TT=1e-3, beta_s=0.2, precision=cases.FP32, max_steps=3),
@@ -85,10 +85,11 @@ def test_mixed_storage_batch(replay, cfg):
     assert all(np.all(np.isfinite(o[k])) for o in out for k in o)
 
 
-def test_fp64_replay_is_the_oracles_step(replay, oracle_mod):
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fp64_replay_is_the_oracles_step(replay, oracle_mod, cfg):
     p = cases.channel(100, 52, 9.0, 4.0, sigma_TT=1e-3, beta_s=0.2)
     p.update(t_bc=[1, 1, 1, 1], psi_bc=[0, 0, 1, 1], psi_w=[0.0, 0.0, 0.2, 0.05])
-    out = run(replay, [p], 3, 1, "fp64")[0]
+    out = run(replay, [p], 3, cfg, f"fp64_{cfg}")[0]
     o = oracle_mod.Oracle(p)
     o.step(3)
     of = o.fields()

@@ -72,12 +72,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def config_tag(config: str) -> str:
+    """File-name form of a configuration name ("tile 64x8/512" -> "tile64x8-512")."""
+    return config.replace(" ", "").replace("/", "-")
+
+
 def measured_traffic(workload: str, config: str) -> int | None:
     """HBM bytes per step launch from the committed counter summary of this
-    workload and kernel configuration ("tile 64x4", "walk 64x4"), or None
-    when there is none or the kernel sources have changed since the counters
-    were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_{config.replace(' ', '')}_hbm_traffic.md")
+    workload and kernel configuration ("tile 64x4/256", "tile 64x8/512"), or
+    None when there is none or the kernel sources have changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_{config_tag(config)}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -128,7 +133,7 @@ def measure(name: str, steps: int, warmup: int) -> dict:
     alg = sum(p["nx"] * p["ny"] * BYTES_PER_NODE[p["precision"]] for p in ps)
     s = lbm.Solver(ps)
     s.autotune(5)
-    s.step(warmup)
+    warm_graphs(s, steps, warmup)
     s.synchronize()
     t0 = time.perf_counter()
     s.step(steps)
@@ -137,13 +142,44 @@ def measure(name: str, steps: int, warmup: int) -> dict:
     s.set_kernel_timing(2)
     s.step(min(steps, 100))
     kms, _ = s.kernel_time_ms()
-    shape = lbm.tile_shapes()[s.tile]
-    kind = lbm.tile_kinds()[s.tile]
+    config = lbm.config_name(s.tile)
     s.close()
     del s
     torch.cuda.empty_cache()
     return {"workload": name, "cases": len(ps), "nodes": cells, "MLUPS": round(cells * steps / dt / 1e6, 1),
-            "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "config": f"{kind} {shape[0]}x{shape[1]}"}
+            "frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "config": config}
+
+
+CHUNK = 100  # steps per captured graph (lbm_step)
+
+
+def warm_graphs(s, steps: int, warmup: int):
+    """Untimed warm-up: `warmup` steps, then one step chunk of every size the
+    timed `steps` will launch, so that no graph is captured or instantiated
+    inside the timed region."""
+    s.step(warmup)
+    for k in sorted({min(steps, CHUNK), steps % CHUNK} - {0}):
+        s.step(k)
+
+
+def calibrate_counters(mib: int = 1024, reps: int = 5):
+    """A plain elementwise kernel of known size for calibrating the HBM byte
+    counters: y = x + 1 over float32 tensors of `mib` MiB, `reps` dispatches,
+    each reading and writing exactly `mib` MiB.  Under rocprofv3 --pmc
+    FETCH_SIZE (then WRITE_SIZE) the known bytes over the counted bytes of
+    this kernel are the factors that convert the step kernel's counters."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise SystemExit("--calibrate-counters needs a GPU")
+    n = mib * (1 << 20) // 4
+    x = torch.zeros(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.add(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel": "elementwise add (float32)", "bytes_read_per_dispatch": n * 4,
+                      "bytes_written_per_dispatch": n * 4, "dispatches": reps}), flush=True)
 
 
 def main():
@@ -157,7 +193,13 @@ def main():
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison workloads (plain FP32 single channel, FP16 storage, batched)")
+    ap.add_argument("--calibrate-counters", action="store_true",
+                    help="run only the elementwise kernel of known size that calibrates FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
+
+    if args.calibrate_counters:
+        calibrate_counters()
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -180,10 +222,10 @@ def main():
         s.set_tile(args.tile)
     elif not args.no_autotune:
         s.autotune(10)
-    shape = lbm.tile_shapes()[s.tile]
-    log(f"workload {args.workload}: {len(ps)} case(s), {cells} nodes, tile {shape}")
+    config = lbm.config_name(s.tile)
+    log(f"workload {args.workload}: {len(ps)} case(s), {cells} nodes, {config}")
 
-    s.step(args.warmup)
+    warm_graphs(s, args.steps, args.warmup)
     s.synchronize()
     # timed region: the production path (captured graphs of 100 steps), HIP
     # events on the launch stream around each launched chunk
@@ -200,7 +242,6 @@ def main():
     s.step(min(args.steps, 200))
     kms_only, _ = s.kernel_time_ms()
     s.set_kernel_timing(0)
-    kind = lbm.tile_kinds()[s.tile]
     for i in range(min(len(ps), 4)):
         d = s.reduce(i)
         log(f"case {i}: step {d['step']} xc {d['xc']:.3f} ux {d['ux']:.3e} nonfinite {d['nonfinite']}")
@@ -222,11 +263,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "cases": len(ps), "nodes": cells,
                    "grids": sorted({f"{p['nx']}x{p['ny']}" for p in ps}),
-                   "kernel_config": f"{kind} {shape[0]}x{shape[1]}", "parallelism": "single GPU"},
+                   "kernel_config": config, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, f"{kind} {shape[0]}x{shape[1]}"),
-                     "kernel": "k_step" if kind == "tile" else "k_walk", "avg_launch_ms": round(kms, 5),
+                     "traffic": measured_traffic(args.workload, config),
+                     "kernel": "k_step", "avg_launch_ms": round(kms, 5),
                      "launches": nlaunch, "kernel_only_ms": round(kms_only, 5),
                      "alg_bytes_per_launch": alg_bytes},
     }

@@ -208,20 +208,23 @@ int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
 /* Step-kernel configuration.  Index i < lbm_tile_count() selects one
  * workgroup per bx x by tile of the handle's tile table (kind 0), the tile
  * plus its halo staged in LDS each step:
- *   0: 64 x 8 tiles, two nodes per thread, each set pulled again right
- *      before its collision;
- *   1: 64 x 4 tiles, one node per thread, its 36 populations held in
- *      registers from the moment pass to the collision (the default).
- * Both compute the same step (results agree to rounding of identical
+ *   0: 64 x 8 tiles, 256 threads, two nodes per thread, each set pulled
+ *      again right before its collision;
+ *   1: 64 x 4 tiles, 256 threads, one node per thread, its 36 populations
+ *      held in registers from the moment pass to the collision (the default);
+ *   2: 64 x 8 tiles, 512 threads, one node per thread as in 1, with half
+ *      the halo per node.
+ * All compute the same step (results agree to rounding of identical
  * operations).  lbm_autotune times every configuration valid for this
  * handle's cases (a trial step re-reads the current state and writes only
  * the scratch half of the ping-pong pair, so the state is unchanged) and
  * keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
- * lbm_tile_shape / lbm_tile_kind describe an index (LBM_E_INVAL if out of
- * range). */
+ * lbm_tile_shape / lbm_tile_threads / lbm_tile_kind describe an index
+ * (LBM_E_INVAL if out of range). */
 int lbm_autotune(lbm_handle* h, int32_t trial_steps);
 int lbm_tile_count(void);
 int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by);
+int lbm_tile_threads(int32_t index);
 int lbm_tile_kind(int32_t index);
 int lbm_set_tile(lbm_handle* h, int32_t index);
 int lbm_get_tile(lbm_handle* h);

@@ -1146,6 +1146,12 @@ int lbm_tile_shape(int32_t index, int32_t* bx, int32_t* by)
     return LBM_OK;
 }
 
+int lbm_tile_threads(int32_t index)
+{
+    if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);
+    return kConfigs[index].nt;
+}
+
 int lbm_tile_kind(int32_t index)
 {
     if (index < 0 || index >= kNumConfigs) return fail(LBM_E_INVAL, "tile index %d out of range", index);

@@ -103,6 +103,7 @@ def lib():
         L.lbm_tile_count.argtypes = []
         L.lbm_tile_shape.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
         L.lbm_tile_kind.argtypes = [i32]
+        L.lbm_tile_threads.argtypes = [i32]
         L.lbm_set_tile.argtypes = [vp, i32]
         L.lbm_get_tile.argtypes = [vp]
         L.lbm_set_graph.argtypes = [vp, i32]
@@ -128,6 +129,23 @@ def tile_shapes() -> list[tuple[int, int]]:
         _check(lib().lbm_tile_shape(i, C.byref(bx), C.byref(by)))
         out.append((bx.value, by.value))
     return out
+
+
+def tile_threads() -> list[int]:
+    """Threads per workgroup of every step configuration index."""
+    out = []
+    for i in range(lib().lbm_tile_count()):
+        n = int(lib().lbm_tile_threads(i))
+        if n <= 0:
+            _check(n)
+        out.append(n)
+    return out
+
+
+def config_name(index: int) -> str:
+    """'tile BXxBY/threads' of a step configuration index."""
+    bx, by = tile_shapes()[index]
+    return f"{tile_kinds()[index]} {bx}x{by}/{tile_threads()[index]}"
 
 
 KINDS = {0: "tile"}

@@ -37,24 +37,32 @@ def test_unknown_workload_is_rejected():
 
 
 def test_traffic_lookup_matches_committed_summary():
-    """The summary under profiles/ is found for its own workload and kernel
-    configuration, and only while the kernel sources hash to the recorded value."""
-    path = os.path.join(ROOT, "profiles", "k_step_fp32_1024x512x4_tile64x4_hbm_traffic.md")
-    kv = {}
-    with open(path) as f:
-        for line in f:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                kv[k.strip()] = v.strip().strip("`")
-    got = bench.measured_traffic("fp32_1024x512x4", "tile 64x4")
-    if kv["kernel_source_sha256"] == bench.kernel_source_hash():
-        assert got == int(kv["traffic_bytes_per_launch"])
-        # traffic is at least the algorithmic bytes of one step
-        assert got >= int(kv["algorithmic_bytes_per_launch"])
-    else:
-        assert got is None
-    assert bench.measured_traffic("fp32_1024x512x4", "tile 64x8") is None
-    assert bench.measured_traffic("no_such_workload", "tile 64x4") is None
+    """Every traffic summary under profiles/ is found for its own workload and
+    kernel configuration, and only while the kernel sources hash to the
+    recorded value."""
+    paths = [p for p in os.listdir(os.path.join(ROOT, "profiles")) if p.endswith("_hbm_traffic.md")]
+    assert paths
+    for name in paths:
+        kv = {}
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            for line in f:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].split(": ", 1)
+                    kv[k.strip()] = v.strip().strip("`")
+        assert name == f"k_step_{kv['workload']}_{bench.config_tag(kv['config'])}_hbm_traffic.md"
+        got = bench.measured_traffic(kv["workload"], kv["config"])
+        if kv["kernel_source_sha256"] == bench.kernel_source_hash():
+            assert got == int(kv["traffic_bytes_per_launch"])
+            # traffic is at least the algorithmic bytes of one step
+            assert got >= int(kv["algorithmic_bytes_per_launch"])
+        else:
+            assert got is None
+        assert bench.measured_traffic(kv["workload"], "tile 32x32/1024") is None
+        assert bench.measured_traffic("no_such_workload", kv["config"]) is None
+
+
+def test_config_tags():
+    assert bench.config_tag("tile 64x8/512") == "tile64x8-512"
 
 
 def test_more_than_one_gpu_is_refused():

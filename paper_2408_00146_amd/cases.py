@@ -248,3 +248,28 @@ def srf_scales(p: dict) -> dict:
     M12 = abs(p["sigma_T"] + p["sigma_TT"]) / p["sigma0"]
     Uo = p["sigma0"] / (p["rho_A"] * p["nu_A"]) * (p["R"] / p["nx"]) * M12
     return {"Uo": Uo, "To": p["R"] / Uo}
+
+
+# ------------------------------------------------- buoyancy-driven rising bubble
+
+def rising_bubble(Eo: float, Re: float = 35.0, D: float = 80.0, nx: int = 161, ny: int = 481,
+                  yc: float = 120.0, U0: float = 0.02, rho_ratio: float = 1000.0, mu_ratio: float = 100.0,
+                  W: float = 5.0, M_phi: float = 0.1, precision: int = FP32) -> dict:
+    """The rising bubble of Sec. 5.3 from its groups, in lattice units:
+    nx x ny lattice, periodic in x, no-slip walls at the bottom and top, a
+    bubble of diameter D centred at ((nx - 1)/2, yc), buoyancy
+    F_y = -(rho - rho_A) g.  Gravitational velocity U0 = sqrt(g D) (chosen),
+    Re = rho_A U0 D / mu_A and Eo = rho_A U0^2 D / sigma fix mu_A and sigma;
+    rho_B = rho_A / rho_ratio, mu_B = mu_A / mu_ratio.  Time scale D / U0.
+    The bubble starts at its Laplace pressure sigma / R; T and psi play no
+    part (uniform T, no surfactant)."""
+    g = U0 * U0 / D
+    mu_A = U0 * D / Re  # rho_A = 1
+    sigma = U0 * U0 * D / Eo
+    rho_B = 1.0 / rho_ratio
+    nu_B = mu_A / mu_ratio / rho_B
+    return base(nx=nx, ny=ny, precision=precision, wall=[0, 0, 1, 1], t_bc=[0, 0, 0, 0], psi_bc=[0, 0, 0, 0],
+                gradT=0.0, sigma_law=SIGMA_MULT, sigma0=sigma, sigma_T=0.0, sigma_TT=0.0, beta_s=0.0,
+                rho_A=1.0, rho_B=rho_B, nu_A=mu_A, nu_B=nu_B, alpha_A=0.05, alpha_B=0.05, W=W, M_phi=M_phi,
+                gravity=g, xc=(nx - 1) / 2.0, yc=yc, R=D / 2.0, psi_band=0.0, psi_bulk=0.0, phi_noise=0.0,
+                p_jump=sigma / (D / 2.0), s_lam=0.0, w_lam=0.0)

@@ -216,9 +216,10 @@ int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
  *      the halo per node.
  * All compute the same step (results agree to rounding of identical
  * operations).  lbm_autotune times every configuration valid for this
- * handle's cases (a trial step re-reads the current state and writes only
- * the scratch half of the ping-pong pair, so the state is unchanged) and
- * keeps the fastest; it synchronizes.  lbm_set_tile picks one by index;
+ * handle's cases over trial_steps steps, in three interleaved rounds, and
+ * keeps the one with the best time (a trial step re-reads the current state
+ * and writes only the scratch half of the ping-pong pair, so the state is
+ * unchanged); it synchronizes.  lbm_set_tile picks one by index;
  * lbm_tile_shape / lbm_tile_threads / lbm_tile_kind describe an index
  * (LBM_E_INVAL if out of range). */
 int lbm_autotune(lbm_handle* h, int32_t trial_steps);

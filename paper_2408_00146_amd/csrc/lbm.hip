@@ -1179,37 +1179,45 @@ int lbm_autotune(lbm_handle* h, int32_t trial_steps)
     CHECK_H(h);
     if (trial_steps <= 0) return fail(LBM_E_INVAL, "trial_steps must be > 0");
     const int keep = h->cfg;
-    int best = keep;
-    float best_ms = 1e30f;
+    // configurations timed in interleaved rounds, each keeping its best time:
+    // the candidates differ by a few per cent, as much as one trial's noise
+    constexpr int kRounds = 3;
+    float best_ms[kNumConfigs];
+    for (float& v : best_ms) v = 1e30f;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     int rc = LBM_OK;
-    for (int s = 0; s < kNumConfigs && rc == LBM_OK; ++s) {
-        if (!config_ok(s, h->fp64)) continue;
-        h->cfg = s;
-        // t = 0 every time: each trial re-reads the current state and rewrites
-        // the scratch half of the ping-pong pair, leaving the state unchanged.
-        for (int w = 0; w < 2 && rc == LBM_OK; ++w) rc = h->launch_step(0);
-        if (rc != LBM_OK) break;
-        if (hipEventRecord(a, h->stream) != hipSuccess) { rc = fail(LBM_E_DEVICE, "event"); break; }
-        for (int t = 0; t < trial_steps && rc == LBM_OK; ++t) rc = h->launch_step(0);
-        if (rc != LBM_OK) break;
-        if (hipEventRecord(b, h->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
-            rc = fail(LBM_E_DEVICE, "event");
-            break;
-        }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = s;
+    for (int round = 0; round < kRounds && rc == LBM_OK; ++round) {
+        for (int s = 0; s < kNumConfigs && rc == LBM_OK; ++s) {
+            if (!config_ok(s, h->fp64)) continue;
+            h->cfg = s;
+            // t = 0 every time: each trial re-reads the current state and rewrites
+            // the scratch half of the ping-pong pair, leaving the state unchanged.
+            for (int w = 0; w < 2 && rc == LBM_OK; ++w) rc = h->launch_step(0);
+            if (rc != LBM_OK) break;
+            if (hipEventRecord(a, h->stream) != hipSuccess) {
+                rc = fail(LBM_E_DEVICE, "event");
+                break;
+            }
+            for (int t = 0; t < trial_steps && rc == LBM_OK; ++t) rc = h->launch_step(0);
+            if (rc != LBM_OK) break;
+            if (hipEventRecord(b, h->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                rc = fail(LBM_E_DEVICE, "event");
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, a, b);
+            best_ms[s] = std::min(best_ms[s], ms);
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     h->cfg = keep;
     if (rc != LBM_OK) return rc;
+    int best = keep;
+    for (int s = 0; s < kNumConfigs; ++s)
+        if (best_ms[s] < best_ms[best]) best = s;
     return lbm_set_tile(h, best);
 }
 

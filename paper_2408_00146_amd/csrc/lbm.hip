@@ -126,7 +126,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_of(ST,
     if (!tile_live(cases, tr, steps, t, b)) return;  // uniform over the block
     const CaseDev& cd = cases[tr.c];
     Ctx<R> c;
-    c.load(cd);
+    c.template load<!(ST == ST_F32 && NT == 512)>(cd);
     const MacroOut mo{nullptr, 0u, nullptr};
     run_tile<R, S, BX, BY, MODE_STEP, NT>(cd, c, tr.x0, tr.y0, b, sh, mo, nullptr);
 }
@@ -575,6 +575,17 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
     d.buf[1] = b1;
     d.rbuf[0] = (__half*)r0;
     d.rbuf[1] = (__half*)r1;
+    ConstsF& f = d.f32;
+    for (int s = 0; s < 4; ++s) f.psi_w[s] = (float)d.psi_w[s];
+    f.T0 = (float)d.T0; f.gradT = (float)d.gradT; f.xT0 = (float)d.xT0;
+    f.s0 = (float)d.s0; f.sT = (float)d.sT; f.sTT = (float)d.sTT; f.Tref = (float)d.Tref; f.beta = (float)d.beta;
+    f.inv_psi_inf = (float)d.inv_psi_inf;
+    f.rhoA = (float)d.rhoA; f.drho = (float)d.drho; f.muA = (float)d.muA; f.dmu = (float)d.dmu;
+    f.alphaA = (float)d.alphaA; f.dalpha = (float)d.dalpha;
+    f.om_phi = (float)d.om_phi; f.om_psi = (float)d.om_psi; f.Mphi = (float)d.Mphi; f.W = (float)d.W;
+    f.Dpsi = (float)d.Dpsi; f.s_lam = (float)d.s_lam; f.w_lam = (float)d.w_lam;
+    f.Fx = (float)d.Fx; f.Fy = (float)d.Fy; f.grav = (float)d.grav;
+    f.scale = (float)d.scale; f.inv_scale = (float)d.inv_scale;
     return d;
 }
 

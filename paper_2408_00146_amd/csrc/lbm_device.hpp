@@ -48,6 +48,19 @@ enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16S = 2 };
 constexpr int kFp16Scale = 1024;
 
 // ------------------------------------------------------- case parameters
+// The step's per-case constants in FP32, converted once on the host, so that
+// a tile can load them as scalars instead of converting each into a vector
+// register of every thread.
+struct ConstsF {
+    float psi_w[4];
+    float T0, gradT, xT0;
+    float s0, sT, sTT, Tref, beta, inv_psi_inf;
+    float rhoA, drho, muA, dmu, alphaA, dalpha;
+    float om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
+    float Fx, Fy, grav;
+    float scale, inv_scale;
+};
+
 // Device copy of one case, precomputed on the host.
 struct CaseDev {
     int32_t nx, ny, pitch, prec;
@@ -68,6 +81,7 @@ struct CaseDev {
     int32_t pad0;
     void* buf[2];       // ping-pong population buffers
     __half* rbuf[2];    // per-node references [plane][4 = phi, psi, p*, T] of each buffer (refs only)
+    ConstsF f32;        // the constants above in FP32 (same rounding as a device conversion)
 };
 
 struct TileRec {
@@ -88,10 +102,15 @@ struct Ctx {
     R om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     R Fx, Fy, grav, scale, inv_scale;
     R pw0, pw1, pw2, pw3;  // psi wall values as separate fields (selected without memory access)
-    // surface tension and the wall-temperature law in FP64 (sigma and its
-    // gradient are formed in FP64 in every precision)
-    double T0d, gradTd, xT0d, s0d, sTd, sTTd, Trefd, betad, ipsid;
 
+    // SC: FP32 constants as scalars (host-converted) rather than converted
+    // into vector registers.  It cuts the FP16-storage 64 x 8 step from 118
+    // to 91 vector registers (4 % faster) and the FP32 64 x 4 step from 128
+    // (with spills) to 111 (5 % faster).  The FP32 64 x 8 step of 512 threads
+    // keeps the conversions: there the scalar constants and the scalar
+    // streaming offsets together exceed the scalar register file, and the
+    // compiler's scalar spills into vector lanes cost more (2 % slower).
+    template <bool SC = false>
     __device__ void load(const CaseDev& c)
     {
         nx = c.nx; ny = c.ny; pitch = c.pitch; wallx = c.wallx; wally = c.wally; law = c.law;
@@ -100,15 +119,20 @@ struct Ctx {
         tbc = (c.tbc[0] ? 1 : 0) | (c.tbc[1] ? 2 : 0) | (c.tbc[2] ? 4 : 0) | (c.tbc[3] ? 8 : 0);
         pbc = (c.pbc[0] ? 1 : 0) | (c.pbc[1] ? 2 : 0) | (c.pbc[2] ? 4 : 0) | (c.pbc[3] ? 8 : 0);
         psi_w = c.psi_w;
-        T0 = R(c.T0); gradT = R(c.gradT); xT0 = R(c.xT0);
-        s0 = R(c.s0); sT = R(c.sT); sTT = R(c.sTT); Tref = R(c.Tref); beta = R(c.beta); inv_psi_inf = R(c.inv_psi_inf);
-        rhoA = R(c.rhoA); drho = R(c.drho); muA = R(c.muA); dmu = R(c.dmu); alphaA = R(c.alphaA); dalpha = R(c.dalpha);
-        om_phi = R(c.om_phi); om_psi = R(c.om_psi); Mphi = R(c.Mphi); W = R(c.W); Dpsi = R(c.Dpsi);
-        s_lam = R(c.s_lam); w_lam = R(c.w_lam); Fx = R(c.Fx); Fy = R(c.Fy); grav = R(c.grav);
-        scale = R(c.scale); inv_scale = R(c.inv_scale);
-        pw0 = R(c.psi_w[0]); pw1 = R(c.psi_w[1]); pw2 = R(c.psi_w[2]); pw3 = R(c.psi_w[3]);
-        T0d = c.T0; gradTd = c.gradT; xT0d = c.xT0; s0d = c.s0; sTd = c.sT; sTTd = c.sTT; Trefd = c.Tref;
-        betad = c.beta; ipsid = c.inv_psi_inf;
+        if constexpr (SC && sizeof(R) == 4) consts(c.f32);
+        else consts(c);
+    }
+    // K: CaseDev (FP64) or ConstsF (FP32), which name their constants alike
+    template <typename K>
+    __device__ void consts(const K& k)
+    {
+        T0 = R(k.T0); gradT = R(k.gradT); xT0 = R(k.xT0);
+        s0 = R(k.s0); sT = R(k.sT); sTT = R(k.sTT); Tref = R(k.Tref); beta = R(k.beta); inv_psi_inf = R(k.inv_psi_inf);
+        rhoA = R(k.rhoA); drho = R(k.drho); muA = R(k.muA); dmu = R(k.dmu); alphaA = R(k.alphaA); dalpha = R(k.dalpha);
+        om_phi = R(k.om_phi); om_psi = R(k.om_psi); Mphi = R(k.Mphi); W = R(k.W); Dpsi = R(k.Dpsi);
+        s_lam = R(k.s_lam); w_lam = R(k.w_lam); Fx = R(k.Fx); Fy = R(k.Fy); grav = R(k.grav);
+        scale = R(k.scale); inv_scale = R(k.inv_scale);
+        pw0 = R(k.psi_w[0]); pw1 = R(k.psi_w[1]); pw2 = R(k.psi_w[2]); pw3 = R(k.psi_w[3]);
     }
     __device__ bool t_dir(int side) const { return (tbc >> side) & 1; }
     __device__ bool p_dir(int side) const { return (pbc >> side) & 1; }
@@ -116,7 +140,6 @@ struct Ctx {
     __device__ R psi_wall_sel(int side) const { return side == 0 ? pw0 : (side == 1 ? pw1 : (side == 2 ? pw2 : pw3)); }
     // Imposed linear wall-temperature law.
     __device__ R Tlaw(R x) const { return T0 + gradT * (x - xT0); }
-    __device__ double Tlaw_d(double x) const { return T0d + gradTd * (x - xT0d); }
 };
 
 // ------------------------------------------------------------ storage codec
@@ -454,7 +477,7 @@ __device__ __forceinline__ R pull_fix(const Ctx<R>& c, S raw, int ux, int uy, in
     }
     if (SET == SET_H) {
         // T_w at the link midpoint minus the node's reference
-        const R d = R(c.Tlaw_d((double)mx - 0.5 * EX) - (double)base);
+        const R d = c.Tlaw(R(mx) - R(0.5 * EX)) - base;
         if ((l.wy && c.t_dir(YS)) || (l.wx && c.t_dir(XS))) val = -val + R(2) * w * d;
     }
     if (SET == SET_Q) {
@@ -629,30 +652,21 @@ __device__ __forceinline__ R sum9(const R v[9])
 
 // ------------------------------------------------------ material laws
 // Surface tension (Sec. 2.1): law 1 as printed, law 0 the multiplicative
-// Langmuir variant; the log argument is floored at 1e-6.  Evaluated in FP64:
-// along the channel sigma changes by ~1e-3 of itself per node, so its
-// gradient is a difference that FP32 would resolve only to ~1e-4.  The
-// surfactant factor ln(1 - psi/psi_inf) varies by O(1) of itself across an
-// interface, so with FP32 / FP16 storage (psi itself carried in FP32) it is
-// formed in FP32: logf of x = 1 - frac rounded to FP32, plus the first-order
-// term of that rounding, (1 - frac - x) / x (a few ulp of the log over the
-// whole clamped range, where log1pf of an FP32 frac loses digits near 1).
+// Langmuir variant; the log argument is floored at 1e-6.  Evaluated in the
+// compute type, as everything else in the step: in FP32 the rounding of
+// sigma (a few 1e-11 of its ~1e-3) reaches the Marangoni force through the
+// isotropic gradient as node-to-node noise, which leaves the FP32 velocity
+// error against the FP64 oracle within a few per cent of what an FP64 sigma
+// gives.
 template <typename R>
-__device__ __forceinline__ double sigma_of(const Ctx<R>& c, double T, double psi)
+__device__ __forceinline__ R sigma_of(const Ctx<R>& c, R T, R psi)
 {
-    const double dT = T - c.Trefd;
-    double frac = psi * c.ipsid;
-    frac = frac > 1.0 - 1e-6 ? 1.0 - 1e-6 : frac;
-    double L;
-    if (sizeof(R) == 8) {
-        L = log(1.0 - frac);
-    } else {
-        const double xe = 1.0 - frac;
-        const float x = (float)xe;
-        L = (double)(logf(x) + (float)(xe - (double)x) * __frcp_rn(x));
-    }
-    if (c.law == 1) return c.s0d + c.s0d * c.betad * (T / c.Trefd) * L + c.sTd * dT + c.sTTd * dT * dT;
-    return (c.s0d + c.sTd * dT + c.sTTd * dT * dT) * (1.0 + c.betad * L);
+    const R dT = T - c.Tref;
+    R frac = psi * c.inv_psi_inf;
+    frac = frac > R(1.0 - 1e-6) ? R(1.0 - 1e-6) : frac;
+    const R L = log(R(1) - frac);
+    if (c.law == 1) return c.s0 + c.s0 * c.beta * (T / c.Tref) * L + c.sT * dT + c.sTT * dT * dT;
+    return (c.s0 + c.sT * dT + c.sTT * dT * dT) * (R(1) + c.beta * L);
 }
 
 // Derivative of the surfactant potential over lambda (Sec. 2):
@@ -870,7 +884,7 @@ struct Smem {
     R rt[N3];   // T reference
     R phd[W2 * H2];
     R phb[N2B];
-    double sg[W1 * H1];  // sigma (FP64)
+    R sg[W1 * H1];       // sigma
     R ps[W1 * H1];   // p* (deviation from its reference with reduced-precision storage)
     R psb[N1B];      // p* reference
     R ts[W1 * H1];   // T - T_w(x): deviation from the linear wall law at the slot's column
@@ -939,7 +953,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
     auto ref_p = [&](int ux, int uy) -> R { return REFS ? sh.rp[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
     auto ref_t = [&](int ux, int uy) -> R { return REFS ? sh.rt[(uy - y0 + 3) * W3 + (ux - x0 + 3)] : R(0); };
     // T - T_w(ux) of a slot from its reference and the sum of its h deviations
-    auto t_dev = [&](int ux, R bt, R sum) -> R { return R((double)bt - c.Tlaw_d((double)ux)) + sum; };
+    auto t_dev = [&](int ux, R bt, R sum) -> R { return (bt - c.Tlaw(R(ux))) + sum; };
     // lattice node of an unwrapped coordinate on a periodic axis
     auto wrapx = [&](int u) { return INT || c.wallx ? u : (u < 0 ? u + c.nx : (u >= c.nx ? u - c.nx : u)); };
     auto wrapy = [&](int u) { return INT || c.wally ? u : (u < 0 ? u + c.ny : (u >= c.ny ? u - c.ny : u)); };
@@ -1205,13 +1219,17 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                 const int e1 = (ly - 1) * W1 + (lx - 1), m1 = (mly - 1) * W1 + (mlx - 1);
                 sh.ps[e1] = sh.ps[m1];
                 if (REFS) sh.psb[e1] = sh.psb[m1];
-                double T = c.Tlaw_d((double)mux) + (double)sh.ts[m1];
+                // T = T_w(a) + d with a = mux, d = ts of the mirror node; the
+                // mirror 2 T_w(m) - T about a Dirichlet wall is T_w(2m - a) - d
+                // (T_w is affine), so the ghost's ts is G (a - ux) + d, with no
+                // difference of O(1) temperatures
+                R a = R(mux), d = sh.ts[m1];
                 R q = sh.pq[m1];
-                if (ys >= 0 && c.t_dir(ys)) T = 2.0 * c.Tlaw_d((double)mx) - T;
-                if (xs >= 0 && c.t_dir(xs)) T = 2.0 * c.Tlaw_d(xs ? c.nx - 0.5 : -0.5) - T;
+                if (ys >= 0 && c.t_dir(ys)) { a = R(2 * mx) - a; d = -d; }
+                if (xs >= 0 && c.t_dir(xs)) { a = (xs ? R(2 * c.nx - 1) : R(-1)) - a; d = -d; }
                 if (ys >= 0 && c.p_dir(ys)) q = R(2) * c.psi_wall(ys) - q;
                 if (xs >= 0 && c.p_dir(xs)) q = R(2) * c.psi_wall(xs) - q;
-                sh.ts[e1] = R(T - c.Tlaw_d((double)ux));
+                sh.ts[e1] = c.gradT * (a - R(ux)) + d;
                 sh.pq[e1] = q;
             }
         }
@@ -1230,7 +1248,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         sh.nx[e] = gx * imag;
         sh.ny[e] = gy * imag;
         const int ux = x0 - 1 + e % W1;
-        sh.sg[e] = sigma_of(c, c.Tlaw_d((double)ux) + (double)sh.ts[e], (double)sh.pq[e]);
+        sh.sg[e] = sigma_of(c, c.Tlaw(R(ux)) + sh.ts[e], sh.pq[e]);
     }
     __syncthreads();
 
@@ -1258,12 +1276,11 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
                        (NX[p1 + W1 + 1] - NX[p1 + W1 - 1] + NX[p1 - W1 + 1] - NX[p1 - W1 - 1]) +
                        (NY[p1 + W1 + 1] - NY[p1 - W1 + 1] + NY[p1 + W1 - 1] - NY[p1 - W1 - 1])) *
                       R(1.0 / 12.0);
-        double dsxd, dsyd;
-        grad2<R, false, double>(sh.sg, nullptr, p1, W1, dsxd, dsyd);
-        const R dsx = R(dsxd), dsy = R(dsyd);
+        R dsx, dsy;
+        grad2<R, false, R>(sh.sg, nullptr, p1, W1, dsx, dsy);
         R dpx, dpy;
         grad2<R, REFS, R>(sh.ps, sh.psb, p1, W1, dpx, dpy);
-        const R sig = R(sh.sg[p1]);
+        const R sig = sh.sg[p1];
         const R pbase = REFS ? sh.psb[p1] : R(0);
         const R pstar = pbase + sh.ps[p1];
 

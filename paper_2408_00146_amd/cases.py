@@ -261,6 +261,9 @@ def rising_bubble(Eo: float, Re: float = 35.0, D: float = 80.0, nx: int = 161, n
     F_y = -(rho - rho_A) g.  Gravitational velocity U0 = sqrt(g D) (chosen),
     Re = rho_A U0 D / mu_A and Eo = rho_A U0^2 D / sigma fix mu_A and sigma;
     rho_B = rho_A / rho_ratio, mu_B = mu_A / mu_ratio.  Time scale D / U0.
+    The light phase of the pressure-based scheme is compressed by about
+    rho_A U0^2 / (rho_B cs^2), so U0 must stay well below 0.3 / rho_ratio
+    for phi to stay near 1 inside the bubble.
     The bubble starts at its Laplace pressure sigma / R; T and psi play no
     part (uniform T, no surfactant)."""
     g = U0 * U0 / D

@@ -690,3 +690,36 @@ def test_rising_bubble_eo_sweep(env):
     assert all(v > 0.1 for v in speed)
     assert all(a > b for a, b in zip(speed, speed[1:])), speed
     assert abs(aspect[0] - 1.0) < 0.05 and all(a > 1.2 for a in aspect[1:]), aspect
+
+
+def test_rising_bubble_density_ratio_100_low_mach(env):
+    """Sec. 5.3's bubble at density ratio 100 (viscosity ratio 100, Re = 35)
+    with the gravitational velocity lowered to U0 = 1e-3: the light phase of
+    the pressure-based scheme has the bulk modulus rho_B cs^2, so it is
+    compressed by ~ rho_A U0^2 / (rho_B cs^2) and phi rises above 1 by as
+    much, while rho(phi) vanishes at phi = 1 + rho_B / (rho_A - rho_B); U0
+    well below 0.3 / (density ratio) keeps the overshoot small.  Eo = 10 and
+    50 in one FP32 handle, to t* = 3 (240 000 steps): both rise at a steady
+    0.2 - 0.35 U0, keep their area within 1 % and phi below 1.001, and
+    flatten (width / height > 1.2), Eo = 10 more than Eo = 50."""
+    lbm, _ = env
+    U0, D = 1e-3, 80.0
+    T = int(D / U0)
+    eos = (10.0, 50.0)
+    ps = [cases.rising_bubble(eo, U0=U0, rho_ratio=100.0) for eo in eos]
+    s = lbm.Solver(ps)
+    s.step(T)
+    y1 = [s.reduce(i)["yc"] for i in range(len(ps))]
+    s.step(2 * T)
+    speed, aspect = [], []
+    for i in range(len(ps)):
+        d = s.reduce(i)
+        assert d["nonfinite"] == 0 and d["phi_max"] < 1.001, (eos[i], d)
+        speed.append((d["yc"] - y1[i]) / (2 * T) / U0)
+        m = np.asarray(s.fields(i, names=("phi",))["phi"]) > 0.5
+        ys, xs = np.nonzero(m)
+        aspect.append((xs.max() - xs.min() + 1) / (ys.max() - ys.min() + 1))
+        assert abs(m.sum() / (np.pi * (D / 2) ** 2) - 1.0) < 0.01, (eos[i], m.sum())
+    print("density ratio 100: rise speed / U0", speed, "width / height", aspect)
+    assert all(0.2 < v < 0.35 for v in speed), speed
+    assert all(a > 1.2 for a in aspect) and aspect[0] > aspect[1], aspect

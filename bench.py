@@ -63,12 +63,16 @@ KERNEL_SOURCES = ("paper_2408_00146_amd/csrc/lbm.hip", "paper_2408_00146_amd/csr
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources with comments and whitespace removed, so
+    that a measured traffic figure stays tied to the code, not its comments."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            src = re.sub(r"/\*.*?\*/|//[^\n]*", " ", f.read(), flags=re.S)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

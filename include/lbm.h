@@ -42,14 +42,14 @@ typedef enum {
     LBM_E_STATE = -5      /* call not valid in the handle's current state */
 } lbm_status;
 
-/* Population storage per case.  Collision arithmetic is FP64 for LBM_FP64 and
- * FP32 otherwise (sigma and its gradient are always FP64).  LBM_FP32 and
+/* Population storage per case.  The step computes in FP64 for LBM_FP64 and
+ * in FP32 otherwise (FP64 only in the diagnostic reductions).  LBM_FP32 and
  * LBM_FP16S store deviations from the rest equilibrium of a per-node
  * reference, X_a - w_a X_ref(x), scaled by 1 (FP32) or 2^10 (FP16): X_ref is
  * the FP16-rounded phi, p*, T and psi of the node that wrote the value for f,
- * g, h and q (kept in four FP16 planes next to each population buffer).
- * LBM_FP64 stores the populations themselves.  Every entry point exchanges
- * full FP64 values. */
+ * g, h and q (one 8-byte record of four FP16 values per node, next to each
+ * population buffer).  LBM_FP64 stores the populations themselves.  Every
+ * entry point exchanges full FP64 values. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16S = 2 } lbm_precision;
 
 /* Surface tension equation of state (Sec. 2.1). */

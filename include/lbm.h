@@ -211,9 +211,10 @@ int lbm_reduce(lbm_handle* h, int32_t case_id, lbm_diag* out);
  *   0: 64 x 8 tiles, 256 threads, two nodes per thread, each set pulled
  *      again right before its collision;
  *   1: 64 x 4 tiles, 256 threads, one node per thread, its 36 populations
- *      held in registers from the moment pass to the collision (the default);
+ *      held in registers from the moment pass to the collision (the default
+ *      of an FP64 handle);
  *   2: 64 x 8 tiles, 512 threads, one node per thread as in 1, with half
- *      the halo per node.
+ *      the halo per node (the default of an FP32 / FP16-storage handle).
  * All compute the same step (results agree to rounding of identical
  * operations).  lbm_autotune times every configuration valid for this
  * handle's cases over trial_steps steps, in three interleaved rounds, and

@@ -43,7 +43,9 @@ struct Config {
 };
 constexpr Config kConfigs[] = {{0, 256}, {1, 256}, {0, 512}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
-constexpr int kDefaultConfig = 1;
+// Configuration of a new handle: the 64 x 4 tile for FP64, the 64 x 8 tile of
+// 512 threads otherwise (the fastest of each on the benchmark workloads).
+constexpr int default_config(bool fp64) { return fp64 ? 1 : 2; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
 // Each XCD works through one contiguous band of the tile table: the halo
@@ -682,7 +684,7 @@ struct lbm_handle {
     Layout L{};
     bool fp64 = false;
     int st = ST_F32;  // ST_F64, or ST_F32 for FP32 / FP16-storage handles (one kernel per storage type)
-    int cfg = kDefaultConfig;  // step configuration (index into kConfigs)
+    int cfg = 1;               // step configuration (index into kConfigs), set by lbm_init
     bool use_graph = true;
     int timing = 0;  // 0 off, 1 per-step eager launches, 2 per launched chunk
     std::map<int, hipGraphExec_t> graphs;
@@ -837,7 +839,7 @@ int lbm_init(const lbm_case* cases, int32_t ncases, void* workspace, size_t byte
         h->st = any64 ? ST_F64 : ST_F32;
     }
     h->steps.assign(ncases, 0);
-    h->cfg = kDefaultConfig;
+    h->cfg = default_config(any64);
 
     size_t o = L.off_pops;
     for (int i = 0; i < ncases; ++i) {

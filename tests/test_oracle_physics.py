@@ -122,8 +122,20 @@ def test_laplace_law(O):
 def test_laplace_law_density_ratio_1000(O):
     """Static bubble at density ratio 1000 and viscosity ratio 100 (the
     Laplace test of Sec. 5.1), started at its Laplace pressure: the pressure
-    jump, averaged over the acoustic oscillation of the box, is sigma / R
-    within 5 % and linear in sigma to 1 % (R = 20, W = 5, 80x80 periodic)."""
+    jump, averaged over the acoustic oscillation of the box, is linear in
+    sigma to 1 % and equals sigma / R times the integral of the discrete CSF
+    weight across the interface, within 1 % (R = 20, W = 5, 80x80 periodic).
+
+    That integral is 1 for the continuous tanh profile (Sec. 3) but 0.960 for
+    the profile sampled at W = 5 with the gradient taken by central
+    differences (what the isotropic stencil reduces to across a flat
+    interface; 0.990 at W = 10, 0.997 at W = 20): the 4 % by which the jump
+    falls short of sigma / R is this discretisation of the CSF weight, the
+    same at every R and density ratio."""
+    x = np.arange(-100, 101, dtype=float)
+    phi0 = 0.5 * (1.0 + np.tanh(2.0 * x / 5.0))
+    weight = 1.5 * 5.0 * np.sum(((phi0[2:] - phi0[:-2]) / 2.0) ** 2)
+    assert 0.955 < weight < 0.965
     R = 20.0
     dps = []
     for sigma in (1e-3, 4e-3):
@@ -136,7 +148,7 @@ def test_laplace_law_density_ratio_1000(O):
             samples.append(d["p_in"] - d["p_out"])
         assert d["nonfinite"] == 0 and d["phi_max"] < 1.001
         dps.append(float(np.mean(samples)))
-        assert dps[-1] == pytest.approx(sigma / R, rel=0.05)
+        assert dps[-1] == pytest.approx(weight * sigma / R, rel=0.01)
     assert dps[1] / dps[0] == pytest.approx(4.0, rel=0.01)
 
 

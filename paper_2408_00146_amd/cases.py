@@ -206,7 +206,7 @@ def srf_channel(M1: float = 0.0, M2: float = 5.0, beta: float = 0.0, psi_L: floa
                 L: int = 600, D_over_H: float = 0.1, x0_over_L: float = 0.25, Re: float = 5.0, Ma: float = 0.25,
                 rho_ratio: float = 1000.0, mu_ratio: float = 100.0, sigma0: float = 5e-3, W: float = 5.0,
                 M_phi: float = 0.1, M_psi: float = 0.01, Pi: float = 8.33, Ex: float = 0.16,
-                precision: int = FP32) -> dict:
+                precision: int = FP32, Uo: float = None) -> dict:
     """The surfactant-laden bubble migration problem of Sec. 2 and Sec. 6 from
     its dimensionless groups, in lattice units.
 
@@ -219,10 +219,18 @@ def srf_channel(M1: float = 0.0, M2: float = 5.0, beta: float = 0.0, psi_L: floa
     Velocity scale U_o = (sigma0/mu_A)(R/L)|M1 + M2| (Sec. 6); Re = U_o R/nu_A
     and Ma = U_o R/alpha_A (Sec. 2.1) fix nu_A and alpha_A (rho_A = 1);
     rho_B = rho_A/rho_ratio, mu_B = mu_A/mu_ratio, alpha_B = alpha_A.
-    Surfactant chemical potential from Pi and Ex; D_psi = M_psi."""
+    Surfactant chemical potential from Pi and Ex; D_psi = M_psi.
+
+    Uo, if given, replaces sigma0 by the value that makes the velocity scale
+    Uo (U_o^2 = sigma0 Re |M1 + M2| / L), every group unchanged: the light
+    phase of the pressure-based scheme is compressed by about
+    rho_A U_o^2 / (rho_B cs^2), so U_o must stay well below 0.3 / rho_ratio
+    (2.5e-4 at the paper's density ratio of 1000)."""
     H = L // 2
     R = 0.5 * D_over_H * H
     dT = 1.0
+    if Uo is not None:
+        sigma0 = Uo * Uo * L / (Re * abs(M1 + M2))
     sT, sTT = M1 * sigma0 / dT, M2 * sigma0 / dT ** 2
     # U_o mu_A is fixed by sigma0, R/L, M1 + M2; Re then fixes mu_A = nu_A (rho_A = 1)
     Uo_muA = sigma0 * (R / L) * abs(M1 + M2)

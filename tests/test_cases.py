@@ -7,14 +7,21 @@ import pytest
 from paper_2408_00146_amd import cases
 
 
+@pytest.mark.parametrize("Uo_set", [None, 2.5e-4])
 @pytest.mark.parametrize("M1,M2,beta,rho_ratio", [(0.0, 5.0, 0.4, 1000.0), (0.0, 1.25, 0.0, 100.0),
                                                   (-2.5, 0.0, 0.2, 1000.0)])
-def test_srf_channel_groups(M1, M2, beta, rho_ratio):
-    p = cases.srf_channel(M1=M1, M2=M2, beta=beta, rho_ratio=rho_ratio)
+def test_srf_channel_groups(M1, M2, beta, rho_ratio, Uo_set):
+    """Every group survives the conversion, also when the velocity scale is
+    set directly (sigma0 then follows from it)."""
+    p = cases.srf_channel(M1=M1, M2=M2, beta=beta, rho_ratio=rho_ratio, Uo=Uo_set)
     L, H, R = p["nx"], p["ny"], p["R"]
     assert (L, H) == (600, 300) and 2 * R == pytest.approx(0.1 * H)
     sc = cases.srf_scales(p)
     Uo = sc["Uo"]
+    if Uo_set is not None:
+        assert Uo == pytest.approx(Uo_set, rel=1e-12)
+    else:
+        assert p["sigma0"] == 5e-3
     muA, muB = p["rho_A"] * p["nu_A"], p["rho_B"] * p["nu_B"]
     # U_o balances the viscous stress mu_A U/R with the thermal Marangoni stress (Sec. 6)
     assert Uo == pytest.approx(p["sigma0"] / muA * (R / L) * abs(M1 + M2), rel=1e-12)

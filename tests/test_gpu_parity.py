@@ -599,6 +599,37 @@ def test_srf_channel_migration(env):
     assert 0.32 < xs[-1] < 0.40, xs
 
 
+def test_srf_channel_density_ratio_1000_low_mach(env):
+    """The migration problem at the paper's density ratio of 1000 with every
+    group kept and sigma0 lowered so that U_o = 2.5e-4, under the light
+    phase's compressibility limit (U_o well below 0.3 / 1000): FP32 fields
+    against the oracle after 20 steps (1e-5 on phi, T, psi, 1e-4 on u, the
+    density-ratio-1000 bars), then the three M2 = 5 runs (beta, psi_L) =
+    (0, 0.4), (0.4, 0.4), (0.4, 0.6) in one handle over 10^6 steps
+    (t* = 17): finite, phi below 1.001, every bubble moving away from
+    x/L = 0.25 towards the cold side, in the order of the printed terminal
+    positions (measured 0.2715, 0.2634, 0.2582).  At U_o = 0.014 (sigma0 =
+    5e-3) the same runs diverge within a few hundred steps."""
+    lbm, O = env
+    p = cases.srf_channel(M2=5.0, beta=0.4, rho_ratio=1000.0, Uo=2.5e-4, precision=cases.FP32)
+    s, o = run_pair(env, p, 20)
+    err = compare(s.fields(), o.fields(), ("phi", "u", "T", "psi"))
+    assert max(err["phi"], err["T"], err["psi"]) <= 1e-5 and err["u"] <= 1e-4, err
+    specs = [(0.0, 0.4), (0.4, 0.4), (0.4, 0.6)]
+    ps = [cases.srf_channel(M2=5.0, beta=b, psi_L=pl, rho_ratio=1000.0, Uo=2.5e-4) for b, pl in specs]
+    s = lbm.Solver(ps)
+    xs = [[0.25] for _ in ps]
+    for _ in range(4):
+        s.step(250_000)
+        for i, q in enumerate(ps):
+            d = s.reduce(i)
+            assert d["nonfinite"] == 0 and d["phi_max"] < 1.001, (specs[i], d)
+            xs[i].append((d["xc"] + 0.5) / q["nx"])
+    print("density ratio 1000, U_o = 2.5e-4: x/L", xs)
+    assert all(all(b > a for a, b in zip(x, x[1:])) for x in xs), xs
+    assert xs[0][-1] > xs[1][-1] > xs[2][-1], xs
+
+
 def test_srf_equilibrium_positions(env):
     """Terminal positions of the paper's self-rewetting migration runs (Sec. 6,
     M1 = 0, M2 = 5, psi from psi_L at the hot wall to psi_R = 0.1 at the

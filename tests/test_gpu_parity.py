@@ -569,6 +569,41 @@ def test_flat_interface_surfactant_equilibrium(env, prec):
 
 # --------------------------------------- the paper's migration problem (Sec. 6)
 
+def test_rising_bubble_density_ratio_1000(env):
+    """Sec. 5.3's bubble at the paper's density ratio of 1000 (viscosity
+    ratio 100, Re = 35) at the light phase's compressibility limit, U0 =
+    3e-4, with the interface widened to W = 12 (at W = 5 a flow inside the
+    light phase grows from the start and the runs diverge near t* = 0.5; at
+    W = 12 it settles at the internal circulation, 0.75 U0): Eo = 0.1 and 10
+    in one FP32 handle to t* = 3 (800 000 steps).  Both stay finite with phi
+    below 1.001 and their area within 1 %; Eo = 0.1 stays circular
+    (width / height < 1.05) and rises faster (measured 0.58 U0 over
+    t* in [1, 3]) than Eo = 10 (0.30 U0), which flattens (width / height
+    1.91).  Eo = 50 and 125 diverge near t* = 1.3 - 1.5 under these
+    settings.  The shapes are parity unpinned."""
+    lbm, _ = env
+    U0, D = 3e-4, 80.0
+    T = int(round(D / U0))
+    eos = (0.1, 10.0)
+    ps = [cases.rising_bubble(eo, U0=U0, rho_ratio=1000.0, W=12.0) for eo in eos]
+    s = lbm.Solver(ps)
+    s.step(T)
+    y1 = [s.reduce(i)["yc"] for i in range(len(ps))]
+    s.step(2 * T)
+    speed, aspect = [], []
+    for i in range(len(ps)):
+        d = s.reduce(i)
+        assert d["nonfinite"] == 0 and d["phi_max"] < 1.001, (eos[i], d)
+        speed.append((d["yc"] - y1[i]) / (2 * T) / U0)
+        m = np.asarray(s.fields(i, names=("phi",))["phi"]) > 0.5
+        ys, xs = np.nonzero(m)
+        aspect.append((xs.max() - xs.min() + 1) / (ys.max() - ys.min() + 1))
+        assert abs(m.sum() / (np.pi * (D / 2) ** 2) - 1.0) < 0.01, (eos[i], m.sum())
+    print("density ratio 1000: rise speed / U0", speed, "width / height", aspect)
+    assert speed[0] > speed[1] > 0.2, speed
+    assert aspect[0] < 1.05 and aspect[1] > 1.5, aspect
+
+
 def test_srf_channel_against_oracle(env):
     """The paper's self-rewetting migration problem (600x300, walls with
     Dirichlet T and psi, printed sigma law, M2 = 5, beta = 0.4) built from its
@@ -704,9 +739,8 @@ def test_rising_bubble_eo_sweep(env):
     flatten (width / height > 1.2); the mean rise speed over t* in [1, 3]
     falls as Eo grows.  Density ratio 10: the light phase's compressibility
     limits U0 to well below 0.3 / (density ratio), see the density-ratio-100
-    test below; at the paper's 1000 the bubble stays bounded only to
-    t* ~ 0.5.  The shapes are parity unpinned (the comparison data the paper
-    cites is not available)."""
+    and 1000 tests below.  The shapes are parity unpinned (the comparison
+    data the paper cites is not available)."""
     lbm, O = env
     U0, D = 0.01, 80.0
     T = int(D / U0)

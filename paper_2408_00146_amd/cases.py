@@ -261,7 +261,7 @@ def srf_scales(p: dict) -> dict:
 # ------------------------------------------------- buoyancy-driven rising bubble
 
 def rising_bubble(Eo: float, Re: float = 35.0, D: float = 80.0, nx: int = 161, ny: int = 481,
-                  yc: float = 120.0, U0: float = 0.02, rho_ratio: float = 1000.0, mu_ratio: float = 100.0,
+                  yc: float = 120.0, U0: float = 0.01, rho_ratio: float = 1000.0, mu_ratio: float = 100.0,
                   W: float = 5.0, M_phi: float = 0.1, precision: int = FP32) -> dict:
     """The rising bubble of Sec. 5.3 from its groups, in lattice units:
     nx x ny lattice, periodic in x, no-slip walls at the bottom and top, a

@@ -569,6 +569,9 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
     d.grav = c.gravity;
     d.scale = c.precision == LBM_FP16S ? (double)kFp16Scale : 1.0;
     d.inv_scale = 1.0 / d.scale;
+    d.a8W2 = 8.0 / (c.W * c.W);
+    d.mt4W = 4.0 * c.M_phi / c.W;
+    d.invTref = c.T_ref != 0 ? 1.0 / c.T_ref : 0.0;
     d.plane = plane_of(c);
     d.max_steps = c.max_steps;
     d.pop_bytes = (uint32_t)case_pop_bytes(c);
@@ -588,6 +591,7 @@ CaseDev make_dev(const lbm_case& c, void* b0, void* b1, void* r0, void* r1)
     f.Dpsi = (float)d.Dpsi; f.s_lam = (float)d.s_lam; f.w_lam = (float)d.w_lam;
     f.Fx = (float)d.Fx; f.Fy = (float)d.Fy; f.grav = (float)d.grav;
     f.scale = (float)d.scale; f.inv_scale = (float)d.inv_scale;
+    f.a8W2 = (float)d.a8W2; f.mt4W = (float)d.mt4W; f.invTref = (float)d.invTref;
     return d;
 }
 

@@ -59,6 +59,7 @@ struct ConstsF {
     float om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     float Fx, Fy, grav;
     float scale, inv_scale;
+    float a8W2, mt4W, invTref;
 };
 
 // Device copy of one case, precomputed on the host.
@@ -73,6 +74,9 @@ struct CaseDev {
     double om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     double Fx, Fy, grav;
     double scale, inv_scale;
+    // quotients of case constants, formed once on the host: 8 / W^2 (surfactant
+    // potential), 4 M_phi / W (phase-field flux), 1 / T_ref (sigma law 1; 0 if T_ref = 0)
+    double a8W2, mt4W, invTref;
     int64_t plane;      // four-set records per direction plane = ny * pitch + pad
     int64_t max_steps;  // <= 0: unlimited
     uint32_t pop_bytes; // bytes of one population buffer (36 planes), < 4 GiB
@@ -101,6 +105,7 @@ struct Ctx {
     R rhoA, drho, muA, dmu, alphaA, dalpha;
     R om_phi, om_psi, Mphi, W, Dpsi, s_lam, w_lam;
     R Fx, Fy, grav, scale, inv_scale;
+    R a8W2, mt4W, invTref;
     R pw0, pw1, pw2, pw3;  // psi wall values as separate fields (selected without memory access)
 
     // SC: FP32 constants as scalars (host-converted) rather than converted
@@ -132,6 +137,7 @@ struct Ctx {
         om_phi = R(k.om_phi); om_psi = R(k.om_psi); Mphi = R(k.Mphi); W = R(k.W); Dpsi = R(k.Dpsi);
         s_lam = R(k.s_lam); w_lam = R(k.w_lam); Fx = R(k.Fx); Fy = R(k.Fy); grav = R(k.grav);
         scale = R(k.scale); inv_scale = R(k.inv_scale);
+        a8W2 = R(k.a8W2); mt4W = R(k.mt4W); invTref = R(k.invTref);
         pw0 = R(k.psi_w[0]); pw1 = R(k.psi_w[1]); pw2 = R(k.psi_w[2]); pw3 = R(k.psi_w[3]);
     }
     __device__ bool t_dir(int side) const { return (tbc >> side) & 1; }
@@ -665,7 +671,7 @@ __device__ __forceinline__ R sigma_of(const Ctx<R>& c, R T, R psi)
     R frac = psi * c.inv_psi_inf;
     frac = frac > R(1.0 - 1e-6) ? R(1.0 - 1e-6) : frac;
     const R L = log(R(1) - frac);
-    if (c.law == 1) return c.s0 + c.s0 * c.beta * (T / c.Tref) * L + c.sT * dT + c.sTT * dT * dT;
+    if (c.law == 1) return c.s0 + c.s0 * c.beta * (T * c.invTref) * L + c.sT * dT + c.sTT * dT * dT;
     return (c.s0 + c.sT * dT + c.sTT * dT * dT) * (R(1) + c.beta * L);
 }
 
@@ -675,8 +681,7 @@ __device__ __forceinline__ R sigma_of(const Ctx<R>& c, R T, R psi)
 template <typename R>
 __device__ __forceinline__ R dV_lam(const Ctx<R>& c, R phi, R omphi)
 {
-    const R a = R(8) / (c.W * c.W);
-    return -c.s_lam * a * R(2) * phi * omphi * (omphi - phi) + c.w_lam * (phi - R(0.5));
+    return -c.s_lam * c.a8W2 * R(2) * phi * omphi * (omphi - phi) + c.w_lam * (phi - R(0.5));
 }
 
 // ----------------------------------------------------------- collisions
@@ -1382,7 +1387,7 @@ __device__ __forceinline__ void tile_body(const Ctx<R>& c, int x0, int y0, View 
         };
         // f: phase field, first-order equilibrium M_phi theta n, theta = 4 phi (1 - phi) / W
         auto do_f = [&](R* f) {
-            const R mt = c.Mphi * R(4) * phi * omphi / c.W;
+            const R mt = c.mt4W * phi * omphi;
             collide_ad<OS>(f, phb, nbf, mt * nxv, mt * nyv, c.om_phi, ux, uy);
         };
         // h: temperature; the new storage reference is the FP16-rounded T of this node

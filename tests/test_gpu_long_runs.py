@@ -115,12 +115,13 @@ def run_logged(s, ncases, steps, every):
     return logs
 
 
-def perturbed(s, ncases, seed=7):
-    """Change every population of every case by one ulp (random sign)."""
+def perturbed(s, ncases, seed=7, rel=2.0 ** -53):
+    """Change every population of every case by `rel` of itself (random sign):
+    one FP64 ulp by default, 2**-24 for one FP32 ulp."""
     rng = np.random.default_rng(seed)
     for i in range(ncases):
         P = s.populations(i)
-        s.set_populations(P * (1 + rng.choice([-1.0, 1.0], size=P.shape) * 2.0 ** -53), i)
+        s.set_populations(P * (1 + rng.choice([-1.0, 1.0], size=P.shape) * rel), i)
 
 
 def test_fp32_channels_20000_steps(lbm):
@@ -197,11 +198,15 @@ def check_against_stored(lbm, s, case, log, z, p, steps, fp32_floor=None):
     operation order) evaluates the same step with other roundings, so its
     distance from the tested configuration, in FP32 and in the FP64 mode, is
     how far two valid evaluations drift apart on this case over this horizon;
-    so are the FP64 mode started one ulp away and the oracle's own source
-    built with FMA contraction (stored beside the reference).  FP64 must stay
-    within three times the largest FP64 spread (at least 1e-12), FP32 within
-    three times the FP32 spread (at least the FP32 bar of 1e-5, or the
-    per-field floors given)."""
+    so are the FP64 mode started one ulp away, the oracle's own source built
+    with FMA contraction (stored beside the reference), and in FP32 the
+    tested configuration started one FP32 ulp away (two draws): where the
+    flow is ill-conditioned, FP32 evaluations that differ only in rounding
+    land on different branches (on the smallest seeded channel after 5000
+    steps, 6e-5 to 2.3e-3 apart in phi).  FP64 must stay within three times
+    the largest FP64 spread (at least 1e-12), FP32 within three times the
+    largest FP32 spread (at least the FP32 bar of 1e-5, or the per-field
+    floors given)."""
     names = list(z["diag_names"])
     ix, iy = names.index("xc"), names.index("yc")
     assert int(z["steps"]) == steps
@@ -209,18 +214,20 @@ def check_against_stored(lbm, s, case, log, z, p, steps, fp32_floor=None):
     dx = max(max(abs(d["xc"] - r[ix]), abs(d["yc"] - r[iy])) for d, r in zip(log, z["diag"]))
     q32, q64 = dict(p, max_steps=0), dict(p, precision=cases.FP64, max_steps=0)
     runs = {}
-    for name, q, cfg, ulp in (("fp32_cfg0", q32, 0, False), ("fp64", q64, t, False),
-                              ("fp64_cfg0", q64, 0, False), ("fp64_ulp", q64, t, True)):
+    for name, q, cfg, ulp in (("fp32_cfg0", q32, 0, None), ("fp32_ulp1", q32, t, (1, 2.0 ** -24)),
+                              ("fp32_ulp2", q32, t, (2, 2.0 ** -24)), ("fp64", q64, t, None),
+                              ("fp64_cfg0", q64, 0, None), ("fp64_ulp", q64, t, (7, 2.0 ** -53))):
         with lbm.Solver(q) as r:
             r.set_tile(cfg)
             if ulp:
-                perturbed(r, 1)
+                perturbed(r, 1, seed=ulp[0], rel=ulp[1])
             r.step(steps)
             runs[name] = sample(r.fields(), z, p)
     g32 = sample(s.fields(case=case), z, p)
     ref = stored(z)
     e32, e64 = errors(g32, ref), errors(runs["fp64"], ref)
-    sp32 = errors(runs["fp32_cfg0"], g32)
+    s32 = [errors(runs[n], g32) for n in ("fp32_cfg0", "fp32_ulp1", "fp32_ulp2")]
+    sp32 = {k: max(e[k] for e in s32) for k in s32[0]}
     a64, b64 = errors(runs["fp64_cfg0"], runs["fp64"]), errors(runs["fp64_ulp"], runs["fp64"])
     c64 = errors(stored(z, "spread_"), ref)
     sp64 = {k: max(a64[k], b64[k], c64[k]) for k in a64}

@@ -58,3 +58,22 @@ def test_oracle_initial_psi_background(oracle_mod):
     expect = p["psi_bulk"] + p["psi_gradx"] * (x - p["xT0"])
     assert np.abs(f["psi"] - expect[None, :]).max() <= 1e-15
     assert f["psi"][0, 0] > f["psi"][0, -1]
+
+
+@pytest.mark.parametrize("Eo,U0,rho_ratio,W", [(0.1, 0.01, 10.0, 5.0), (125.0, 3e-4, 1000.0, 14.0)])
+def test_rising_bubble_groups(Eo, U0, rho_ratio, W):
+    """The rising bubble of Sec. 5.3 keeps its groups in lattice units:
+    Re = rho_A U0 D / mu_A = 35, Eo = rho_A U0^2 D / sigma, U0 = sqrt(g D),
+    the density and viscosity ratios, and the 161x481 box with D = 80 at
+    (80, 120), periodic sides and no-slip bottom and top walls."""
+    p = cases.rising_bubble(Eo, U0=U0, rho_ratio=rho_ratio, W=W)
+    D = 2 * p["R"]
+    muA, muB = p["rho_A"] * p["nu_A"], p["rho_B"] * p["nu_B"]
+    assert (p["nx"], p["ny"], D, p["xc"], p["yc"]) == (161, 481, 80.0, 80.0, 120.0)
+    assert p["wall"] == [0, 0, 1, 1] and p["W"] == W
+    assert p["rho_A"] * U0 * D / muA == pytest.approx(35.0, rel=1e-12)
+    assert p["rho_A"] * U0 ** 2 * D / p["sigma0"] == pytest.approx(Eo, rel=1e-12)
+    assert (p["gravity"] * D) ** 0.5 == pytest.approx(U0, rel=1e-12)
+    assert p["rho_A"] / p["rho_B"] == pytest.approx(rho_ratio, rel=1e-12)
+    assert muA / muB == pytest.approx(100.0, rel=1e-12)
+    assert p["p_jump"] == pytest.approx(p["sigma0"] / p["R"], rel=1e-12)
